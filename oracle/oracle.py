@@ -1,0 +1,251 @@
+"""ctypes wrapper of the C++ oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this module.  It loads ``liborng_oracle.so`` (built from
+``orng_oracle.cc`` by :func:`build`) and returns numpy arrays.  It never
+imports the product package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "orng_oracle.cc")
+LIB = os.path.join(HERE, "liborng_oracle.so")
+
+PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE = range(5)
+U32, F32_UNIFORM, F32_NORMAL = range(3)
+GENS = (PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE)
+DISTS = (U32, F32_UNIFORM, F32_NORMAL)
+
+# contraction off: each float operation in the source is one IEEE operation
+CXXFLAGS = ["-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+            "-pthread"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ into ``oracle/liborng_oracle.so``."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    subprocess.run(["g++", *CXXFLAGS, SRC, "-o", tmp], check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        u32, u64, i32, vp, f32 = C.c_uint32, C.c_uint64, C.c_int, C.c_void_p, C.c_float
+        P32, P64 = C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)
+        sig = {
+            "oracle_philox4x32_10": (None, [P32, P32, P32]),
+            "oracle_threefry4x32_20": (None, [P32, P32, P32]),
+            "oracle_threefry2x64_20": (None, [P64, P64, P64]),
+            "oracle_squares32": (u32, [u64, u64]),
+            "oracle_squares_key": (u64, [u64]),
+            "oracle_tyche_mix": (None, [P32]),
+            "oracle_tyche_init": (None, [u64, u32, u32, P32]),
+            "oracle_tyche_next": (u32, [P32]),
+            "oracle_word": (u32, [i32, u64, u32, u64]),
+            "oracle_sample": (None, [i32, i32, u64, u32, u64, vp]),
+            "oracle_u01": (f32, [u32]),
+            "oracle_ln_u1": (f32, [u32]),
+            "oracle_sincos2pi": (None, [u32, C.POINTER(f32), C.POINTER(f32)]),
+            "oracle_normal_pair": (None, [u32, u32, C.POINTER(f32)]),
+            "oracle_u01_n": (None, [vp, u64, vp]),
+            "oracle_ln_u1_n": (None, [vp, u64, vp]),
+            "oracle_sincos2pi_n": (None, [vp, u64, vp, vp]),
+            "oracle_normal_pair_n": (None, [vp, vp, u64, vp, vp]),
+            "oracle_fill": (i32, [i32, i32, u64, u32, u64, u64, vp, i32]),
+            "oracle_fill_multi": (i32, [i32, i32, u64, u32, u32, u64, u64, vp, i32]),
+            "oracle_samples_at": (None, [i32, i32, u64, vp, vp, u64, vp, i32]),
+            "oracle_walk_sigma": (f32, [f32, f32]),
+            "oracle_brownian": (i32, [u64, u32, vp, u32, u32, u64, u32, f32, f32, vp, vp, u32,
+                                      i32]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def default_threads() -> int:
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
+def _arr32(vals):
+    return (C.c_uint32 * len(vals))(*[int(v) & 0xFFFFFFFF for v in vals])
+
+
+def philox4x32_10(ctr, key):
+    out = (C.c_uint32 * 4)()
+    lib().oracle_philox4x32_10(_arr32(ctr), _arr32(key), out)
+    return list(out)
+
+
+def threefry4x32_20(ctr, key):
+    out = (C.c_uint32 * 4)()
+    lib().oracle_threefry4x32_20(_arr32(ctr), _arr32(key), out)
+    return list(out)
+
+
+def threefry2x64_20(ctr, key):
+    out = (C.c_uint64 * 2)()
+    c = (C.c_uint64 * 2)(*[int(v) & (2**64 - 1) for v in ctr])
+    k = (C.c_uint64 * 2)(*[int(v) & (2**64 - 1) for v in key])
+    lib().oracle_threefry2x64_20(c, k, out)
+    return list(out)
+
+
+def squares32(ctr, key):
+    return lib().oracle_squares32(ctr, key)
+
+
+def squares_key(seed):
+    return lib().oracle_squares_key(seed)
+
+
+def tyche_mix(state):
+    st = _arr32(state)
+    lib().oracle_tyche_mix(st)
+    return list(st)
+
+
+def tyche_init(seed, c_xor, d_xor):
+    st = (C.c_uint32 * 4)()
+    lib().oracle_tyche_init(seed, c_xor, d_xor, st)
+    return list(st)
+
+
+def tyche_stream(seed, c_xor, d_xor, count):
+    st = (C.c_uint32 * 4)()
+    lib().oracle_tyche_init(seed, c_xor, d_xor, st)
+    return [lib().oracle_tyche_next(st) for _ in range(count)]
+
+
+def word(gen, seed, ctr, p):
+    return lib().oracle_word(gen, seed, ctr, p)
+
+
+def u01(x):
+    return lib().oracle_u01(x)
+
+
+def ln_u1(k):
+    return lib().oracle_ln_u1(k)
+
+
+def sincos2pi(k):
+    c, s = C.c_float(), C.c_float()
+    lib().oracle_sincos2pi(k, C.byref(c), C.byref(s))
+    return c.value, s.value
+
+
+def normal_pair(x0, x1):
+    out = (C.c_float * 2)()
+    lib().oracle_normal_pair(x0, x1, out)
+    return out[0], out[1]
+
+
+def u01_n(x):
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    out = np.empty(x.shape, np.float32)
+    lib().oracle_u01_n(x.ctypes.data, x.size, out.ctypes.data)
+    return out
+
+
+def ln_u1_n(k):
+    k = np.ascontiguousarray(k, dtype=np.uint32)
+    out = np.empty(k.shape, np.float32)
+    lib().oracle_ln_u1_n(k.ctypes.data, k.size, out.ctypes.data)
+    return out
+
+
+def sincos2pi_n(k):
+    k = np.ascontiguousarray(k, dtype=np.uint32)
+    c = np.empty(k.shape, np.float32)
+    s = np.empty(k.shape, np.float32)
+    lib().oracle_sincos2pi_n(k.ctypes.data, k.size, c.ctypes.data, s.ctypes.data)
+    return c, s
+
+
+def normal_pair_n(x0, x1):
+    x0 = np.ascontiguousarray(x0, dtype=np.uint32)
+    x1 = np.ascontiguousarray(x1, dtype=np.uint32)
+    z0 = np.empty(x0.shape, np.float32)
+    z1 = np.empty(x0.shape, np.float32)
+    lib().oracle_normal_pair_n(x0.ctypes.data, x1.ctypes.data, x0.size, z0.ctypes.data,
+                               z1.ctypes.data)
+    return z0, z1
+
+
+def _dtype(dist):
+    return np.uint32 if dist == U32 else np.float32
+
+
+def fill(gen, dist, seed, ctr, offset, n, nthreads=None):
+    out = np.empty(n, dtype=_dtype(dist))
+    rc = lib().oracle_fill(gen, dist, seed, ctr, offset, n, out.ctypes.data,
+                           nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_fill rejected arguments (%d)" % rc)
+    return out
+
+
+def fill_multi(gen, dist, seed, ctr0, n_streams, offset, per_stream, nthreads=None):
+    out = np.empty(n_streams * per_stream, dtype=_dtype(dist))
+    rc = lib().oracle_fill_multi(gen, dist, seed, ctr0, n_streams, offset, per_stream,
+                                 out.ctypes.data, nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_fill_multi rejected arguments (%d)" % rc)
+    return out
+
+
+def samples_at(gen, dist, seed, ctrs, pos, nthreads=None):
+    ctrs = np.ascontiguousarray(ctrs, dtype=np.uint32)
+    pos = np.ascontiguousarray(pos, dtype=np.uint64)
+    assert ctrs.shape == pos.shape
+    out = np.empty(pos.shape, dtype=_dtype(dist))
+    lib().oracle_samples_at(gen, dist, seed, ctrs.ctypes.data, pos.ctypes.data, pos.size,
+                            out.ctypes.data, nthreads or default_threads())
+    return out
+
+
+def walk_sigma(dt, D):
+    return lib().oracle_walk_sigma(dt, D)
+
+
+def brownian(seed, ctr0, n_particles=None, ids=None, dim=3, step0=0, n_steps=1, dt=1e-3, D=1.0,
+             pos=None, msd_every=0, nthreads=None):
+    """Returns (pos [dim][count] float32, msd float64 sums or None)."""
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        count = ids.size
+    else:
+        count = n_particles
+    if pos is None:
+        pos = np.zeros((dim, count), dtype=np.float32)
+    else:
+        pos = np.ascontiguousarray(pos, dtype=np.float32).copy()
+    nsnap = n_steps // msd_every if msd_every else 0
+    msd = np.zeros(nsnap, dtype=np.float64) if nsnap else None
+    rc = lib().oracle_brownian(seed, ctr0, ids.ctypes.data if ids is not None else None, count,
+                               dim, step0, n_steps, dt, D, pos.ctypes.data,
+                               msd.ctypes.data if msd is not None else None, msd_every,
+                               nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_brownian rejected arguments (%d)" % rc)
+    return pos, msd

@@ -1,0 +1,322 @@
+"""Pins of the oracle's integer generators against things other than itself.
+
+* Philox4x32-10 and Threefry2x64-20: rocRAND's own block functions (built
+  host-only from its public headers) on random and edge-case keys/counters.
+* Threefry4x32-20: rocRAND implements a different mixing schedule (pairs
+  switch every second round), so the pin is two-step: the big-integer model
+  run with rocRAND's schedule must equal rocRAND (this pins rotations, key
+  schedule, parity constant and injections), and the same model run with the
+  published every-round Threefish permutation must equal the oracle.
+* Tyche's MIX: OpenSSL's ChaCha20 keystream, rebuilt from the oracle's MIX
+  (MIX is the ChaCha quarter round).  Tyche's seeding constants: their closed
+  forms floor(2^32/phi) and floor(2^32/pi).
+* Squares32 and Tyche sequencing: parity unpinned externally; checked against
+  the big-integer transcription and by statistical properties only.
+"""
+import math
+import os
+import random
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import spec_model as S
+from conftest import run_xcheck
+
+U32 = st.integers(0, 2**32 - 1)
+U64 = st.integers(0, 2**64 - 1)
+EDGE32 = [0, 1, 2, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFE, 0xFFFFFFFF]
+
+
+def _rand_cases(n, seed):
+    r = random.Random(seed)
+    cases = []
+    for _ in range(n):
+        cases.append(([r.getrandbits(32) for _ in range(4)], [r.getrandbits(32) for _ in range(4)]))
+    for e in EDGE32:
+        cases.append(([e] * 4, [e] * 4))
+        cases.append(([e, 0, e, 0], [0, e, 0, e]))
+    return cases
+
+
+def test_philox_vs_rocrand(O, rocrand_xcheck):
+    cases = _rand_cases(3000, 1)
+    lines = ["P %d %d %d %d %d %d" % (k[0], k[1], *c) for c, k in cases]
+    got = run_xcheck(rocrand_xcheck, lines)
+    for (c, k), g in zip(cases, got):
+        assert O.philox4x32_10(c, k[:2]) == g, (c, k)
+
+
+def test_threefry2x64_vs_rocrand(O, rocrand_xcheck):
+    r = random.Random(2)
+    cases = [([r.getrandbits(64), r.getrandbits(64)], [r.getrandbits(64), r.getrandbits(64)])
+             for _ in range(3000)]
+    cases += [([e, e], [e, 2**64 - 1 - e]) for e in (0, 1, 2**63, 2**64 - 1)]
+    lines = ["S %d %d %d %d" % (k[0], k[1], c[0], c[1]) for c, k in cases]
+    got = run_xcheck(rocrand_xcheck, lines)
+    for (c, k), g in zip(cases, got):
+        assert O.threefry2x64_20(c, k) == g
+
+
+def test_threefry4x32_machinery_vs_rocrand(rocrand_xcheck):
+    cases = _rand_cases(2000, 3)
+    lines = ["T %d %d %d %d %d %d %d %d" % (*k, *c) for c, k in cases]
+    got = run_xcheck(rocrand_xcheck, lines)
+    for (c, k), g in zip(cases, got):
+        assert S.threefry4x32(c, k, schedule="every_second_round") == g
+
+
+def test_threefry4x32_oracle_vs_published_schedule(O):
+    for c, k in _rand_cases(2000, 4):
+        assert O.threefry4x32_20(c, k) == S.threefry4x32(c, k, schedule="every_round")
+
+
+def test_threefry4x32_schedules_really_differ(O):
+    # guards the two-step pin: if the schedules coincided it would prove nothing
+    c, k = [1, 2, 3, 4], [5, 6, 7, 8]
+    assert S.threefry4x32(c, k, schedule="every_round") != \
+        S.threefry4x32(c, k, schedule="every_second_round")
+
+
+@settings(max_examples=300, deadline=None)
+@given(st.lists(U32, min_size=4, max_size=4), st.lists(U32, min_size=2, max_size=2))
+def test_philox_vs_bigint(O, c, k):
+    assert O.philox4x32_10(c, k) == S.philox4x32_10(c, k)
+
+
+@settings(max_examples=300, deadline=None)
+@given(st.lists(U64, min_size=2, max_size=2), st.lists(U64, min_size=2, max_size=2))
+def test_threefry2x64_vs_bigint(O, c, k):
+    assert O.threefry2x64_20(c, k) == S.threefry2x64_20(c, k)
+
+
+@settings(max_examples=500, deadline=None)
+@given(U64, U64)
+def test_squares_vs_bigint(O, c, k):
+    assert O.squares32(c, k) == S.squares32(c, k)
+
+
+@settings(max_examples=300, deadline=None)
+@given(U64)
+def test_squares_key_vs_bigint(O, seed):
+    key = O.squares_key(seed)
+    assert key == S.squares_key(seed)
+    assert key & 1
+
+
+@settings(max_examples=300, deadline=None)
+@given(st.lists(U32, min_size=4, max_size=4))
+def test_tyche_mix_vs_bigint(O, s):
+    assert O.tyche_mix(s) == list(S.tyche_mix(*s))
+
+
+@settings(max_examples=50, deadline=None)
+@given(U64, U32, U32)
+def test_tyche_outputs_vs_bigint(O, seed, cx, dx):
+    st_ = O.tyche_init(seed, cx, dx)
+    assert len(st_) == 4
+    out = []
+    import ctypes as C
+    arr = (C.c_uint32 * 4)(*st_)
+    for _ in range(40):
+        out.append(O.lib().oracle_tyche_next(arr))
+    assert out == S.tyche_outputs(seed, cx, dx, 40)
+
+
+# ---- Tyche MIX == ChaCha quarter round, pinned by OpenSSL -------------------
+def _chacha20_block_from_mix(O, key_words, counter, nonce_words):
+    x = [0x61707865, 0x3320646E, 0x79622D32, 0x6B206574] + list(key_words) + [counter] + \
+        list(nonce_words)
+    w = list(x)
+
+    def qr(a, b, c, d):
+        w[a], w[b], w[c], w[d] = O.tyche_mix([w[a], w[b], w[c], w[d]])
+
+    for _ in range(10):
+        qr(0, 4, 8, 12); qr(1, 5, 9, 13); qr(2, 6, 10, 14); qr(3, 7, 11, 15)
+        qr(0, 5, 10, 15); qr(1, 6, 11, 12); qr(2, 7, 8, 13); qr(3, 4, 9, 14)
+    out = [(w[i] + x[i]) & 0xFFFFFFFF for i in range(16)]
+    return b"".join(v.to_bytes(4, "little") for v in out)
+
+
+def test_tyche_mix_is_chacha_quarter_round_openssl(O, tmp_path):
+    openssl = shutil.which("openssl")
+    if not openssl:
+        pytest.skip("openssl not available")
+    r = random.Random(5)
+    for trial in range(4):
+        key = bytes(r.getrandbits(8) for _ in range(32))
+        ctr = r.getrandbits(31)
+        nonce = bytes(r.getrandbits(8) for _ in range(12))
+        iv = ctr.to_bytes(4, "little") + nonce
+        nblocks = 3
+        out = tmp_path / ("ks%d.bin" % trial)
+        subprocess.run([openssl, "enc", "-chacha20", "-K", key.hex(), "-iv", iv.hex(),
+                        "-out", str(out)], input=b"\0" * (64 * nblocks), check=True)
+        ks = out.read_bytes()
+        kw = [int.from_bytes(key[4 * i:4 * i + 4], "little") for i in range(8)]
+        nw = [int.from_bytes(nonce[4 * i:4 * i + 4], "little") for i in range(3)]
+        mine = b"".join(_chacha20_block_from_mix(O, kw, ctr + j, nw) for j in range(nblocks))
+        assert mine == ks
+
+
+def _isqrt_frac_floor_phi():
+    # floor(2^32 / phi) = floor(2^33 / (1 + sqrt 5)), exact in integers
+    # 2^33/(1+sqrt5) = 2^33 (sqrt5 - 1)/4 = 2^31 (sqrt5 - 1)
+    s = math.isqrt(5 * 4**80)  # floor(sqrt5 * 2^80)
+    return (2**31 * (s - 2**80)) >> 80
+
+
+def _floor_2p32_over_pi():
+    # Machin: pi = 16 atan(1/5) - 4 atan(1/239), in fixed point with 120 bits
+    P = 120
+    one = 1 << P
+
+    def atan_inv(x):
+        total, term, k, sign = 0, one // x, 1, 1
+        while term:
+            total += sign * (term // k)
+            term //= x * x
+            k += 2
+            sign = -sign
+        return total
+
+    pi = 16 * atan_inv(5) - 4 * atan_inv(239)
+    return (2**32 << P) // pi
+
+
+def test_tyche_constants_closed_form():
+    st_ = S.tyche_outputs  # noqa: F841 (model carries the same literals)
+    assert _isqrt_frac_floor_phi() == 2654435769
+    assert _floor_2p32_over_pi() == 1367130551
+
+
+def test_tyche_constants_in_oracle(O):
+    # init with zero seed and zero indices, zero rounds cannot be observed, so
+    # undo the 20 MIX rounds with the inverse quarter round and read c, d back
+    st_ = O.tyche_init(0, 0, 0)
+
+    def rotr(x, r):
+        return ((x >> r) | (x << (32 - r))) & 0xFFFFFFFF
+
+    a, b, c, d = st_
+    for _ in range(20):
+        b = rotr(b, 7) ^ c; c = (c - d) & 0xFFFFFFFF
+        d = rotr(d, 8) ^ a; a = (a - b) & 0xFFFFFFFF
+        b = rotr(b, 12) ^ c; c = (c - d) & 0xFFFFFFFF
+        d = rotr(d, 16) ^ a; a = (a - b) & 0xFFFFFFFF
+    assert (a, b, c, d) == (0, 0, _isqrt_frac_floor_phi(), _floor_2p32_over_pi())
+
+
+# ---- stream layouts ---------------------------------------------------------
+@pytest.mark.parametrize("gen", range(5))
+def test_word_vs_bigint_layout(O, gen):
+    r = random.Random(10 + gen)
+    for _ in range(60 if gen != 4 else 25):
+        seed, ctr = r.getrandbits(64), r.getrandbits(32)
+        p = r.choice([r.getrandbits(32), r.getrandbits(12), 0, 2**32 - 1, 16383, 16384])
+        assert O.word(gen, seed, ctr, p) == S.word(gen, seed, ctr, p)
+
+
+def test_tyche_substream0_is_textbook(O):
+    seed, ctr = 0x0123456789ABCDEF, 77
+    ref = S.tyche_outputs(seed, 0, ctr, 256)  # textbook Tyche(seed, idx=ctr)
+    pos = [256 * k + w for k in range(64) for w in range(4)]
+    assert [O.word(4, seed, ctr, p) for p in pos] == ref
+
+
+@pytest.mark.parametrize("gen", range(5))
+def test_fill_matches_direct_word(O, gen):
+    # the range fill (block- or substream-wise) against direct per-word evaluation
+    seed, ctr, off = 0xDEADBEEF12345678, 9, 16384 * 3 - 37
+    n = 700
+    f = O.fill(gen, O.U32, seed, ctr, off, n)
+    r = random.Random(gen)
+    for j in r.sample(range(n), 60) + [0, n - 1]:
+        assert int(f[j]) == O.word(gen, seed, ctr, off + j)
+
+
+@pytest.mark.parametrize("gen", range(5))
+@pytest.mark.parametrize("dist", range(3))
+def test_offset_and_chunking_invariance(O, gen, dist):
+    seed, ctr = 123456789, 4
+    full = O.fill(gen, dist, seed, ctr, 0, 40000, nthreads=1)
+    for off, n in [(1, 5), (3, 1000), (16383, 3), (777, 30000), (39999, 1)]:
+        part = O.fill(gen, dist, seed, ctr, off, n, nthreads=3)
+        assert np.array_equal(part.view(np.uint32), full[off:off + n].view(np.uint32))
+    # arbitrary split into chunks
+    cuts = [0, 7, 4096, 4099, 20001, 40000]
+    glued = np.concatenate([O.fill(gen, dist, seed, ctr, a, b - a) for a, b in zip(cuts, cuts[1:])])
+    assert np.array_equal(glued.view(np.uint32), full.view(np.uint32))
+
+
+@pytest.mark.parametrize("gen", range(5))
+def test_thread_count_invariance(O, gen):
+    a = O.fill(gen, O.F32_NORMAL, 5, 6, 11, 50001, nthreads=1)
+    b = O.fill(gen, O.F32_NORMAL, 5, 6, 11, 50001, nthreads=7)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("gen", range(5))
+def test_fill_multi_is_per_stream_fill(O, gen):
+    m = O.fill_multi(gen, O.U32, 42, 100, 37, 5, 9)
+    for i in range(37):
+        assert np.array_equal(m[9 * i:9 * i + 9], O.fill(gen, O.U32, 42, 100 + i, 5, 9))
+
+
+def test_period_bounds(O):
+    with pytest.raises(ValueError):
+        O.fill(0, 0, 1, 1, 2**32 - 3, 4)
+    assert O.fill(0, 0, 1, 1, 2**32 - 4, 4).size == 4
+    assert O.fill(0, 0, 1, 1, 2**32, 0).size == 0
+
+
+# ---- statistical properties (T2: distinct streams, avalanche) ---------------
+@pytest.mark.parametrize("gen", range(5))
+def test_bytes_uniform_chi2(O, gen):
+    from scipy import stats
+    w = O.fill(gen, O.U32, 0x1234, 0, 0, 1 << 18)
+    by = w.view(np.uint8)
+    counts = np.bincount(by, minlength=256)
+    chi2, p = stats.chisquare(counts)
+    assert p > 1e-4, (gen, chi2, p)
+
+
+@pytest.mark.parametrize("gen", range(5))
+def test_avalanche_seed_and_counter(O, gen):
+    # one flipped bit of seed or counter changes each output bit with p = 1/2
+    r = random.Random(20 + gen)
+    n = 256
+    flips = []
+    for _ in range(24):
+        seed, ctr = r.getrandbits(64), r.getrandbits(32)
+        base = O.fill(gen, O.U32, seed, ctr, 0, n)
+        if r.random() < 0.5:
+            other = O.fill(gen, O.U32, seed ^ (1 << r.randrange(64)), ctr, 0, n)
+        else:
+            other = O.fill(gen, O.U32, seed, ctr ^ (1 << r.randrange(32)), 0, n)
+        x = np.bitwise_xor(base, other)
+        flips.append(np.unpackbits(x.view(np.uint8)).mean())
+    f = np.array(flips)
+    # each trial: 8192 bits, sd of the mean ~ 0.0055
+    assert np.all(np.abs(f - 0.5) < 0.03), f
+
+
+@pytest.mark.parametrize("gen", range(5))
+def test_neighbouring_streams_uncorrelated(O, gen):
+    # HOOMD-style parallel streams: 16,000 streams x 3 draws (paper section 5.2)
+    m = O.fill_multi(gen, O.F32_UNIFORM, 99, 0, 16000, 0, 3).reshape(16000, 3).astype(np.float64)
+    a, b = m[:-1, 0], m[1:, 0]
+    rho = np.corrcoef(a, b)[0, 1]
+    assert abs(rho) < 5 / math.sqrt(16000)
+    assert abs(m.mean() - 0.5) < 5 * math.sqrt(1 / 12 / m.size)
+
+
+def test_philox_is_a_bijection_on_counters(O):
+    seen = set()
+    for c in range(1 << 12):
+        seen.add(tuple(O.philox4x32_10([c, 0, 0, 0], [7, 8])))
+    assert len(seen) == 1 << 12
