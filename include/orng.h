@@ -1,0 +1,142 @@
+/*
+ * orng.h -- C interface of liborng, counter-based random number generation
+ * on MI355X (gfx950).
+ *
+ * Stream model (OpenRAND paper, section 3.1 "API Design"): a generator is
+ * addressed by a 64-bit seed and a 32-bit counter; together they name one
+ * stream of period 2^32 words.  The seed identifies a processing element (a
+ * particle, a pixel), the counter gives it as many independent streams as it
+ * needs.  Generation is stateless (section 3.1, second paragraph): every
+ * output is a pure function of (generator, distribution, seed, counter,
+ * position), so results never depend on launch geometry, thread count,
+ * batching, other requests or timing (section 4).
+ *
+ * Generators (section 3.1): Philox4x32-10 and Threefry (4x32-20, 2x64-20)
+ * after Salmon et al. SC'11, Squares (32-bit output, four rounds) after
+ * Widynski 2020, Tyche after Neves and Araujo 2012.
+ *
+ * Conventions shared by every call:
+ *  - Device pointers are caller-owned HIP device allocations; the library never
+ *    frees caller memory.  Output pointers must be 4-byte aligned; 16-byte
+ *    alignment of the block grid (out address in words minus offset being a
+ *    multiple of 4) is the fast path.
+ *  - `stream` is a hipStream_t passed as an opaque pointer (NULL: the null
+ *    stream).  Calls that take a stream enqueue work on it and return at once.
+ *  - Every call returns ORNG_OK (0) or a negative status; none aborts.  After
+ *    ORNG_EHIP, orng_last_hip_error() gives the HIP error code (per thread).
+ *  - n == 0 is a no-op that returns ORNG_OK (pointers may then be NULL).
+ */
+#ifndef ORNG_H
+#define ORNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* generators */
+enum {
+    ORNG_PHILOX4X32_10 = 0,
+    ORNG_THREEFRY4X32_20 = 1,
+    ORNG_THREEFRY2X64_20 = 2,
+    ORNG_SQUARES32 = 3,
+    ORNG_TYCHE = 4
+};
+
+/* distributions; every sample is 4 bytes */
+enum {
+    ORNG_U32 = 0,        /* raw 32-bit word */
+    ORNG_F32_UNIFORM = 1, /* (word >> 8) * 2^-24, in [0, 1) */
+    ORNG_F32_NORMAL = 2  /* Box-Muller, one member of a pair per sample */
+};
+
+/* status codes */
+enum {
+    ORNG_OK = 0,
+    ORNG_EINVAL = -1, /* bad enum, NULL pointer with work to do, misalignment, bad dim */
+    ORNG_ERANGE = -2, /* position past the stream period, counter overflow */
+    ORNG_ENOMEM = -3, /* request larger than the memory it may use */
+    ORNG_EAGAIN = -4, /* resources momentarily exhausted (non-blocking calls) */
+    ORNG_EBUSY = -5,  /* result not ready yet */
+    ORNG_EHIP = -6,   /* HIP runtime error, see orng_last_hip_error() */
+    ORNG_ENOENT = -7  /* unknown ticket / object */
+};
+
+/*
+ * orng_fill -- out[j] = sample (offset + j) of stream (seed, ctr), j < n.
+ *
+ * Paper section 3.1 (stream = seed + counter, period 2^32).  Sample p of a
+ * distribution uses word p (U32, F32_UNIFORM); for F32_NORMAL, sample p is
+ * member p mod 2 of the Box-Muller pair built from words 2*(p/2) and
+ * 2*(p/2)+1.  The stream's words are:
+ *   Philox4x32-10  : word p = word p%4 of Philox(counter (p/4, ctr, 0, 0),
+ *                    key (lo32 seed, hi32 seed))
+ *   Threefry4x32-20: same counter, key (lo32 seed, hi32 seed, 0, 0)
+ *   Threefry2x64-20: counter (p/4, ctr) as 64-bit words, key (seed, 0);
+ *                    words lo X0, hi X0, lo X1, hi X1
+ *   Squares32      : squares32(counter (ctr << 32) | p, key K(seed)),
+ *                    K = SplitMix64 output step of seed, low bit set
+ *   Tyche          : tiles of 16384 words; word p of tile t = p / 16384,
+ *                    r = p % 16384 is output 4*(r/256) + r%4 of the Tyche
+ *                    instance seeded with (seed, ctr) whose c word is XORed
+ *                    with t*64 + (r/4)%64.
+ * Arguments: gen, dist (enums above); d_out: device buffer of n * 4 bytes.
+ * Errors: EINVAL (enum, NULL, alignment), ERANGE (offset + n > 2^32).
+ */
+int orng_fill(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t offset, uint64_t n,
+              void *d_out, void *stream);
+
+/*
+ * orng_fill_multi -- out[i * per_stream + j] = sample (offset + j) of stream
+ * (seed, ctr0 + i), for i < n_streams, j < per_stream.  One seed, many
+ * counters: the "multiple streams per seed" use of section 3.1.
+ * Errors: as orng_fill, plus ERANGE when ctr0 + n_streams - 1 overflows 32 bits.
+ */
+int orng_fill_multi(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t n_streams,
+                    uint64_t offset, uint64_t per_stream, void *d_out, void *stream);
+
+/*
+ * orng_brownian -- fused overdamped Brownian walk (paper section 4, Fig. 1;
+ * section 5.1), all steps in one launch.
+ * Particle i (0 <= i < n_particles) owns the Philox4x32-10 stream
+ * (seed, ctr0 + i).  Global step g = step0 + s (s < n_steps) uses F32_NORMAL
+ * samples dim*g .. dim*g + dim - 1 of that stream and updates
+ * x_d = fmaf(sigma, normal_d, x_d), sigma = (float)sqrt(2.0 * D * dt).
+ * d_pos: float SoA [dim][n_particles], read and written in place.
+ * d_msd: NULL, or n_steps / msd_every doubles; entry q receives the sum over
+ *        all particles of |x|^2 after local step (q + 1) * msd_every (the
+ *        library zeroes it first).  Summation order is not fixed, so d_msd is
+ *        reproducible only to rounding.
+ * Resuming from saved positions with step0 = k continues the same walk.
+ * Errors: EINVAL (dim not 1..3, NULL d_pos), ERANGE (dim*(step0+n_steps) >
+ *         2^32 or ctr0 + n_particles - 1 overflows).
+ */
+int orng_brownian(uint64_t seed, uint32_t ctr0, uint32_t n_particles, uint32_t dim,
+                  uint64_t step0, uint32_t n_steps, float dt, float D, float *d_pos,
+                  double *d_msd, uint32_t msd_every, void *stream);
+
+/* Launch knobs for the fill kernels (0 = automatic).  They change speed
+   only, never results.  Process-wide; NULL restores the defaults. */
+typedef struct {
+    uint32_t wg_size;     /* threads per workgroup: 64..512, multiple of 64 */
+    uint32_t unroll;      /* blocks of 4 words per lane per span: 1..64 */
+    uint32_t max_wgs;     /* cap on the grid; larger work loops grid-stride */
+    uint32_t nontemporal; /* 1 nontemporal stores, 2 ordinary stores */
+} orng_launch_t;
+int orng_set_launch(const orng_launch_t *cfg);
+int orng_get_launch(orng_launch_t *cfg);
+
+/* Text for a status code (static storage). */
+const char *orng_strerror(int status);
+/* HIP error code behind the last ORNG_EHIP on this thread (0 if none). */
+int orng_last_hip_error(void);
+/* Library version, e.g. 0x000100 for 0.1.0. */
+int orng_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ORNG_H */

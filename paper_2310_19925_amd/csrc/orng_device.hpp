@@ -1,0 +1,306 @@
+// Device-side generator cores, float conversions and the Box-Muller normal
+// for gfx950.  Everything here is a __device__ function kept in VGPRs; key
+// material that is the same for every lane of a launch is precomputed once per
+// launch on the host (KeySched) and arrives in SGPRs through the kernarg
+// segment, so the per-block work is only the data-dependent part.
+//
+// Definitions (the paper names the generators in section 3.1 but defines none
+// of them; the round functions follow the primary sources it cites):
+//   Philox4x32-10, Threefry4x32-20, Threefry2x64-20 : Salmon et al., SC'11.
+//   Squares32 (four rounds)                         : Widynski 2020.
+//   Tyche                                           : Neves and Araujo 2012.
+// The stream-to-counter mappings, the float32 uniform, the float32 logarithm
+// and quarter-turn sine/cosine and the Box-Muller pairing are readings of the
+// paper's stream model (section 3.1: 64-bit seed, 32-bit counter, period 2^32
+// words) stated next to each function.  Every float expression below is one
+// IEEE operation (the library is built with -ffp-contract=off); fused
+// multiply-adds are written as fmaf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace orng {
+
+enum GenId : int { G_PHILOX = 0, G_TF4X32 = 1, G_TF2X64 = 2, G_SQUARES = 3, G_TYCHE = 4 };
+enum DistId : int { D_U32 = 0, D_UNIFORM = 1, D_NORMAL = 2 };
+
+// Per-launch key material, uniform across the grid.
+struct KeySched {
+    uint32_t k[10][2];   // Philox round keys (key bumped by the Weyl pair)
+    uint32_t ks4[5];     // Threefry4x32 key schedule: key words + parity word
+    uint64_t ks2[3];     // Threefry2x64 key schedule
+    uint64_t sqkey;      // Squares key derived from the seed
+    uint32_t seed_lo, seed_hi;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10.  Counter (c0, c1, 0, 0): c0 is the block number inside the
+// stream, c1 the stream counter.  The two zero words make the first round's
+// second product vanish; the compiler folds that.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox_block(uint32_t c0, uint32_t c1, const KeySched &ks,
+                                             uint32_t o[4]) {
+    uint32_t x0 = c0, x1 = c1, x2 = 0u, x3 = 0u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)x0 * 0xD2511F53u;
+        const uint64_t b = (uint64_t)x2 * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(b >> 32) ^ x1 ^ ks.k[r][0];
+        const uint32_t n2 = (uint32_t)(a >> 32) ^ x3 ^ ks.k[r][1];
+        x1 = (uint32_t)b;
+        x3 = (uint32_t)a;
+        x0 = n0;
+        x2 = n2;
+    }
+    o[0] = x0; o[1] = x1; o[2] = x2; o[3] = x3;
+}
+
+// ---------------------------------------------------------------------------
+// Threefry4x32-20.  Counter (c0, c1, 0, 0), key (lo seed, hi seed, 0, 0).
+// Mixing pairs follow the Threefish permutation: (0,1)(2,3) on even rounds,
+// (0,3)(2,1) on odd rounds; key injection after every fourth round.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t rotl32(uint32_t x, int r) {
+    return (x << r) | (x >> (32 - r));
+}
+
+template <int R>
+__device__ __forceinline__ void tf4_round(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3) {
+    constexpr int RA[8] = {10, 11, 13, 23, 6, 17, 25, 18};
+    constexpr int RB[8] = {26, 21, 27, 5, 20, 11, 10, 20};
+    if constexpr ((R & 1) == 0) {
+        x0 += x1; x1 = rotl32(x1, RA[R & 7]) ^ x0;
+        x2 += x3; x3 = rotl32(x3, RB[R & 7]) ^ x2;
+    } else {
+        x0 += x3; x3 = rotl32(x3, RA[R & 7]) ^ x0;
+        x2 += x1; x1 = rotl32(x1, RB[R & 7]) ^ x2;
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void tf4_inject(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3,
+                                           const KeySched &ks) {
+    x0 += ks.ks4[(S + 0) % 5];
+    x1 += ks.ks4[(S + 1) % 5];
+    x2 += ks.ks4[(S + 2) % 5];
+    x3 += ks.ks4[(S + 3) % 5] + (uint32_t)S;
+}
+
+template <int S>
+__device__ __forceinline__ void tf4_quad(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3,
+                                         const KeySched &ks) {
+    tf4_round<4 * S - 4>(x0, x1, x2, x3);
+    tf4_round<4 * S - 3>(x0, x1, x2, x3);
+    tf4_round<4 * S - 2>(x0, x1, x2, x3);
+    tf4_round<4 * S - 1>(x0, x1, x2, x3);
+    tf4_inject<S>(x0, x1, x2, x3, ks);
+}
+
+__device__ __forceinline__ void tf4_block(uint32_t c0, uint32_t c1, const KeySched &ks,
+                                          uint32_t o[4]) {
+    uint32_t x0 = c0 + ks.ks4[0], x1 = c1 + ks.ks4[1], x2 = ks.ks4[2], x3 = ks.ks4[3];
+    tf4_quad<1>(x0, x1, x2, x3, ks);
+    tf4_quad<2>(x0, x1, x2, x3, ks);
+    tf4_quad<3>(x0, x1, x2, x3, ks);
+    tf4_quad<4>(x0, x1, x2, x3, ks);
+    tf4_quad<5>(x0, x1, x2, x3, ks);
+    o[0] = x0; o[1] = x1; o[2] = x2; o[3] = x3;
+}
+
+// ---------------------------------------------------------------------------
+// Threefry2x64-20.  Counter (block, stream counter) as 64-bit words, key
+// (seed, 0); the block's four 32-bit words are lo X0, hi X0, lo X1, hi X1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t rotl64(uint64_t x, int r) {
+    return (x << r) | (x >> (64 - r));
+}
+
+template <int S>
+__device__ __forceinline__ void tf2_quad(uint64_t &x0, uint64_t &x1, const KeySched &ks) {
+    constexpr int ROT[8] = {16, 42, 12, 31, 16, 32, 24, 21};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        x0 += x1;
+        x1 = rotl64(x1, ROT[(4 * S - 4 + i) & 7]) ^ x0;
+    }
+    x0 += ks.ks2[S % 3];
+    x1 += ks.ks2[(S + 1) % 3] + (uint64_t)S;
+}
+
+__device__ __forceinline__ void tf2_block(uint32_t c0, uint32_t c1, const KeySched &ks,
+                                          uint32_t o[4]) {
+    uint64_t x0 = (uint64_t)c0 + ks.ks2[0];
+    uint64_t x1 = (uint64_t)c1 + ks.ks2[1];
+    tf2_quad<1>(x0, x1, ks);
+    tf2_quad<2>(x0, x1, ks);
+    tf2_quad<3>(x0, x1, ks);
+    tf2_quad<4>(x0, x1, ks);
+    tf2_quad<5>(x0, x1, ks);
+    o[0] = (uint32_t)x0; o[1] = (uint32_t)(x0 >> 32);
+    o[2] = (uint32_t)x1; o[3] = (uint32_t)(x1 >> 32);
+}
+
+// ---------------------------------------------------------------------------
+// Squares32: counter ((stream counter << 32) | position), key from the seed.
+// x*x + a mod 2^64 is built from one 32x32 low product and one
+// v_mad_u64_u32: x*x = xl*xl + 2*xl*xh*2^32 (mod 2^64), and the low word of
+// (2*xl*xh) << 32 is zero, so the add of a only needs a carry-free high add.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t sq_add(uint64_t x, uint64_t a) {
+    const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
+    const uint32_t cross = xl * xh;
+    const uint64_t addend = a + ((uint64_t)(cross + cross) << 32);
+    return (uint64_t)xl * xl + addend;
+}
+
+__device__ __forceinline__ uint64_t swap32(uint64_t x) { return (x >> 32) | (x << 32); }
+
+__device__ __forceinline__ uint32_t squares_word(uint32_t ctr, uint32_t pos, uint64_t key) {
+    // y = ((ctr << 32) | pos) * key mod 2^64
+    const uint32_t kl = (uint32_t)key, kh = (uint32_t)(key >> 32);
+    const uint32_t hi_add = pos * kh + ctr * kl;
+    const uint64_t y = (uint64_t)pos * kl + ((uint64_t)hi_add << 32);
+    const uint64_t z = y + key;
+    uint64_t x = swap32(sq_add(y, y));
+    x = swap32(sq_add(x, z));
+    x = swap32(sq_add(x, y));
+    return (uint32_t)(sq_add(x, z) >> 32);
+}
+
+// ---------------------------------------------------------------------------
+// Tyche.  MIX is the ChaCha quarter round; seeding puts (hi seed, lo seed,
+// floor(2^32/phi) ^ substream, floor(2^32/pi) ^ counter) in (a, b, c, d) and
+// mixes twenty times; each output mixes once and returns b.  Stream layout:
+// tiles of 16384 words; in tile t, lane l (0..63) owns blocks k*64 + l,
+// k = 0..63, and produces them from substream t*64 + l in order.
+// ---------------------------------------------------------------------------
+struct Tyche {
+    uint32_t a, b, c, d;
+    __device__ __forceinline__ void mix() {
+        a += b; d = rotl32(d ^ a, 16);
+        c += d; b = rotl32(b ^ c, 12);
+        a += b; d = rotl32(d ^ a, 8);
+        c += d; b = rotl32(b ^ c, 7);
+    }
+    __device__ __forceinline__ void seed(const KeySched &ks, uint32_t substream, uint32_t ctr) {
+        a = ks.seed_hi;
+        b = ks.seed_lo;
+        c = 2654435769u ^ substream;
+        d = 1367130551u ^ ctr;
+#pragma unroll 4
+        for (int i = 0; i < 20; ++i) mix();
+    }
+    __device__ __forceinline__ uint32_t next() {
+        mix();
+        return b;
+    }
+    __device__ __forceinline__ void next4(uint32_t o[4]) {
+        o[0] = next(); o[1] = next(); o[2] = next(); o[3] = next();
+    }
+};
+
+constexpr uint32_t TYCHE_TILE_WORDS = 16384;
+constexpr uint32_t TYCHE_TILE_BLOCKS = 4096;
+
+// ---------------------------------------------------------------------------
+// float32 conversions.
+//   uniform  : (x >> 8) * 2^-24, exact, in [0, 1 - 2^-24].
+//   ln_u1(k) : ln(k * 2^-24) for k in [1, 2^24]: k = m 2^e with m in
+//              [sqrt(1/2), sqrt(2)) read from the float's bits, ln m =
+//              2 atanh(s), s = (m-1)/(m+1), series to s^9, then the exponent
+//              part with a two-piece ln 2 (high piece exact times e-24).
+//   sincos   : cos, sin of 2 pi k/2^24 for k in [0, 2^24): nearest quarter
+//              turn j and signed remainder d in integers, theta = d * (float(2
+//              pi) 2^-24), Taylor polynomials to theta^9 / theta^10, rotate by j.
+//   normal   : (R cos 2 pi u2, R sin 2 pi u2), R = sqrt(-2 ln u1) with
+//              u1 = ((x0>>8)+1) 2^-24 from the even word and u2 = (x1>>8) 2^-24
+//              from the odd word of each pair (Box and Muller 1958).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float to_uniform(uint32_t x) {
+    return __uint2float_rn(x >> 8) * 0x1p-24f;
+}
+
+__device__ __forceinline__ float ln_u1(uint32_t k) {
+    const float f = __uint2float_rn(k);  // exact, k <= 2^24
+    const uint32_t bits = __float_as_uint(f);
+    const int ebias = (int)(bits >> 23) - 127;
+    const float m1 = __uint_as_float((bits & 0x007FFFFFu) | 0x3F800000u);  // [1, 2)
+    const bool low = m1 < 0x1.6a09e6p+0f;
+    const float m = low ? m1 : m1 * 0.5f;
+    const int e = low ? ebias : ebias + 1;
+    const float s = (m - 1.0f) / (m + 1.0f);
+    const float z = s * s;
+    float q = fmaf(z, (float)(2.0 / 9.0), (float)(2.0 / 7.0));
+    q = fmaf(z, q, (float)(2.0 / 5.0));
+    q = fmaf(z, q, (float)(2.0 / 3.0));
+    q = z * q;
+    const float lnm = fmaf(s, q, s + s);
+    const float t = (float)(e - 24);
+    return fmaf(t, 0x1.62e4p-1f, fmaf(t, 0x1.7f7d1cp-20f, lnm));
+}
+
+__device__ __forceinline__ void sincos_turn(uint32_t k, float &c, float &s) {
+    const uint32_t q = (k + 0x200000u) >> 22;
+    const int d = (int)k - (int)(q << 22);
+    const float th = (float)d * (0x1.921fb6p+2f * 0x1p-24f);
+    const float z = th * th;
+    float ps = fmaf(z, (float)(1.0 / 362880.0), (float)(-1.0 / 5040.0));
+    ps = fmaf(z, ps, (float)(1.0 / 120.0));
+    ps = fmaf(z, ps, (float)(-1.0 / 6.0));
+    const float sn = fmaf(th * z, ps, th);
+    float pc = fmaf(z, (float)(-1.0 / 3628800.0), (float)(1.0 / 40320.0));
+    pc = fmaf(z, pc, (float)(-1.0 / 720.0));
+    pc = fmaf(z, pc, (float)(1.0 / 24.0));
+    pc = fmaf(z, pc, -0.5f);
+    const float cs = fmaf(z, pc, 1.0f);
+    const uint32_t j = q & 3u;
+    // rotate (cs, sn) by j quarter turns
+    const float cr = (j & 1u) ? sn : cs;
+    const float sr = (j & 1u) ? cs : sn;
+    c = ((j + 1u) & 2u) ? -cr : cr;   // j = 1, 2 negate cos
+    s = (j & 2u) ? -sr : sr;          // j = 2, 3 negate sin
+}
+
+__device__ __forceinline__ void normal_pair(uint32_t x0, uint32_t x1, float &z0, float &z1) {
+    const float l = ln_u1((x0 >> 8) + 1u);
+    const float r = __builtin_sqrtf(-2.0f * l);
+    float c, s;
+    sincos_turn(x1 >> 8, c, s);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// Convert a block of four words to four output samples (bit patterns).
+template <int D>
+__device__ __forceinline__ void convert4(uint32_t w[4]) {
+    if constexpr (D == D_UNIFORM) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = __float_as_uint(to_uniform(w[i]));
+    } else if constexpr (D == D_NORMAL) {
+        float a, b, c, d;
+        normal_pair(w[0], w[1], a, b);
+        normal_pair(w[2], w[3], c, d);
+        w[0] = __float_as_uint(a); w[1] = __float_as_uint(b);
+        w[2] = __float_as_uint(c); w[3] = __float_as_uint(d);
+    }
+}
+
+// Words of counter block `blk` (positions 4*blk .. 4*blk+3) of stream ctr.
+template <int G>
+__device__ __forceinline__ void counter_block(uint32_t blk, uint32_t ctr, const KeySched &ks,
+                                              uint32_t w[4]) {
+    if constexpr (G == G_PHILOX) {
+        philox_block(blk, ctr, ks, w);
+    } else if constexpr (G == G_TF4X32) {
+        tf4_block(blk, ctr, ks, w);
+    } else if constexpr (G == G_TF2X64) {
+        tf2_block(blk, ctr, ks, w);
+    } else {  // G_SQUARES: four independent words
+        const uint32_t p = blk << 2;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = squares_word(ctr, p + (uint32_t)i, ks.sqkey);
+    }
+}
+
+}  // namespace orng

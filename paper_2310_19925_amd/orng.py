@@ -1,0 +1,137 @@
+"""Thin ctypes binding of liborng.so (include/orng.h).
+
+Argument marshalling only: every call goes straight to the C entry point of the
+same name, which enqueues HIP kernels on the given (or current) stream.  The
+library must have been built (``python -m paper_2310_19925_amd.build`` or
+``__graft_entry__.build()``); importing this module fails loudly otherwise --
+there is no CPU fallback.  PyTorch is used only for device buffers and
+streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborng.so")
+
+PHILOX4X32_10, THREEFRY4X32_20, THREEFRY2X64_20, SQUARES32, TYCHE = range(5)
+U32, F32_UNIFORM, F32_NORMAL = range(3)
+OK, EINVAL, ERANGE, ENOMEM, EAGAIN, EBUSY, EHIP, ENOENT = 0, -1, -2, -3, -4, -5, -6, -7
+
+
+class OrngError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.orng_strerror(status).decode()
+        if status == EHIP:
+            msg += " (hip error %d)" % _lib.orng_last_hip_error()
+        super().__init__("%s: %s [%d]" % (where, msg, status))
+
+
+class orng_launch_t(C.Structure):
+    _fields_ = [("wg_size", C.c_uint32), ("unroll", C.c_uint32), ("max_wgs", C.c_uint32),
+                ("nontemporal", C.c_uint32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liborng.so is not built (%s); run paper_2310_19925_amd/build.py"
+                          % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    i32, u32, u64, vp, f32 = C.c_int, C.c_uint32, C.c_uint64, C.c_void_p, C.c_float
+    sig = {
+        "orng_fill": [i32, i32, u64, u32, u64, u64, vp, vp],
+        "orng_fill_multi": [i32, i32, u64, u32, u32, u64, u64, vp, vp],
+        "orng_brownian": [u64, u32, u32, u32, u64, u32, f32, f32, vp, vp, u32, vp],
+        "orng_set_launch": [C.POINTER(orng_launch_t)],
+        "orng_get_launch": [C.POINTER(orng_launch_t)],
+        "orng_last_hip_error": [],
+        "orng_version": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = i32
+    L.orng_strerror.argtypes = [i32]
+    L.orng_strerror.restype = C.c_char_p
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(status, where):
+    if status != OK:
+        raise OrngError(status, where)
+
+
+def orng_fill(gen, dist, seed, ctr, offset, n, out, stream=None):
+    _check(_lib.orng_fill(gen, dist, seed, ctr, offset, n, _ptr(out), _stream(stream)),
+           "orng_fill")
+
+
+def orng_fill_multi(gen, dist, seed, ctr0, n_streams, offset, per_stream, out, stream=None):
+    _check(_lib.orng_fill_multi(gen, dist, seed, ctr0, n_streams, offset, per_stream, _ptr(out),
+                                _stream(stream)), "orng_fill_multi")
+
+
+def orng_brownian(seed, ctr0, n_particles, dim, step0, n_steps, dt, D, pos, msd=None,
+                  msd_every=0, stream=None):
+    _check(_lib.orng_brownian(seed, ctr0, n_particles, dim, step0, n_steps, dt, D, _ptr(pos),
+                              _ptr(msd), msd_every, _stream(stream)), "orng_brownian")
+
+
+def orng_set_launch(wg_size=0, unroll=0, max_wgs=0, nontemporal=0):
+    cfg = orng_launch_t(wg_size, unroll, max_wgs, nontemporal)
+    _check(_lib.orng_set_launch(C.byref(cfg)), "orng_set_launch")
+
+
+def orng_reset_launch():
+    _check(_lib.orng_set_launch(None), "orng_set_launch")
+
+
+def orng_get_launch():
+    cfg = orng_launch_t()
+    _check(_lib.orng_get_launch(C.byref(cfg)), "orng_get_launch")
+    return dict(wg_size=cfg.wg_size, unroll=cfg.unroll, max_wgs=cfg.max_wgs,
+                nontemporal=cfg.nontemporal)
+
+
+# -------- convenience wrappers that allocate the output tensor ---------------
+def fill(gen, dist, seed, ctr, offset, n, device="cuda", stream=None):
+    """Returns a new device tensor (uint32 viewed as int32 for U32, float32 otherwise)."""
+    import torch
+    dt = torch.int32 if dist == U32 else torch.float32
+    out = torch.empty(n, dtype=dt, device=device)
+    orng_fill(gen, dist, seed, ctr, offset, n, out, stream)
+    return out
+
+
+def fill_multi(gen, dist, seed, ctr0, n_streams, offset, per_stream, device="cuda", stream=None):
+    import torch
+    dt = torch.int32 if dist == U32 else torch.float32
+    out = torch.empty(n_streams * per_stream, dtype=dt, device=device)
+    orng_fill_multi(gen, dist, seed, ctr0, n_streams, offset, per_stream, out, stream)
+    return out

@@ -1,0 +1,169 @@
+"""GPU parity of the fill paths against the oracle (bit-exact, every generator
+and distribution), through the C-ABI.
+
+Small cases are compared element by element: they span several spans/tiles
+and end in a ragged tail.  The 2^30-sample bulk configuration is compared on
+sampled positions (the oracle evaluates each one directly) and through
+properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GENS = range(5)
+DISTS = range(3)
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_19925_amd import orng
+    orng.orng_reset_launch()
+    return orng
+
+
+def as_u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint32)
+
+
+def _case(R, O, gen, dist, seed, ctr, off, n, pad=0):
+    """Fill through the C-ABI into a buffer starting `pad` words into an
+    allocation (pad != 0 makes the output misaligned w.r.t. 16 bytes)."""
+    print("case gen=%d dist=%d seed=%d ctr=%d off=%d n=%d pad=%d" % (gen, dist, seed, ctr, off, n,
+                                                                    pad), flush=True)
+    buf = torch.full((n + pad + 4,), -1, dtype=torch.int32, device="cuda")
+    out = buf[pad:pad + n]
+    R.orng_fill(gen, dist, seed, ctr, off, n, out)
+    torch.cuda.synchronize()
+    got = as_u32(out)
+    ref = bits(O.fill(gen, dist, seed, ctr, off, n))
+    bad = np.nonzero(got != ref)[0]
+    assert bad.size == 0, "first mismatch at %d of %d" % (bad[0], n)
+    # nothing written outside [pad, pad + n)
+    rest = as_u32(buf)
+    assert np.all(rest[:pad] == 0xFFFFFFFF) and np.all(rest[pad + n:] == 0xFFFFFFFF)
+
+
+@pytest.mark.parametrize("gen", GENS)
+@pytest.mark.parametrize("dist", DISTS)
+def test_fill_parity_small(R, O, gen, dist):
+    n = 3 * 16384 + 4 * 517 + 3  # several tiles/spans + ragged tail
+    _case(R, O, gen, dist, 0x0123456789ABCDEF, 7, 0, n)
+    _case(R, O, gen, dist, 42, 0, 5, n)               # odd offset: pairs split
+    _case(R, O, gen, dist, 2**64 - 1, 2**32 - 1, 16381, 40000)
+
+
+@pytest.mark.parametrize("gen", GENS)
+@pytest.mark.parametrize("pad", [1, 2, 3])
+def test_fill_parity_misaligned(R, O, gen, pad):
+    for dist in DISTS:
+        _case(R, O, gen, dist, 99 + pad, 3, 4 * 1000, 9001, pad=pad)
+        _case(R, O, gen, dist, 99 + pad, 3, 4 * 1000 + pad, 9001, pad=pad)  # realigned
+
+
+@pytest.mark.parametrize("gen", GENS)
+def test_fill_tiny_and_edges(R, O, gen):
+    for dist in DISTS:
+        for off, n in [(0, 1), (1, 1), (3, 2), (0, 3), (0, 5), (63, 65), (2**32 - 1, 1),
+                       (2**32 - 7, 7), (2**32 - 16384 * 2 - 5, 16384 * 2 + 5)]:
+            _case(R, O, gen, dist, 5, 6, off, n)
+
+
+def test_fill_errors(R):
+    out = torch.empty(16, dtype=torch.int32, device="cuda")
+    with pytest.raises(R.OrngError) as e:
+        R.orng_fill(5, 0, 1, 1, 0, 4, out)
+    assert e.value.status == R.EINVAL
+    with pytest.raises(R.OrngError) as e:
+        R.orng_fill(0, 3, 1, 1, 0, 4, out)
+    assert e.value.status == R.EINVAL
+    with pytest.raises(R.OrngError) as e:
+        R.orng_fill(0, 0, 1, 1, 2**32 - 3, 4, out)
+    assert e.value.status == R.ERANGE
+    with pytest.raises(R.OrngError) as e:
+        R.orng_fill(0, 0, 1, 1, 0, 4, out.data_ptr() + 2)
+    assert e.value.status == R.EINVAL
+    with pytest.raises(R.OrngError) as e:
+        R.orng_fill(0, 0, 1, 1, 0, 4, 0)
+    assert e.value.status == R.EINVAL
+    R.orng_fill(0, 0, 1, 1, 2**32, 0, 0)  # n == 0 is a no-op
+    with pytest.raises(R.OrngError) as e:
+        R.orng_fill_multi(0, 0, 1, 2**32 - 2, 3, 0, 4, out)
+    assert e.value.status == R.ERANGE
+
+
+def test_plain_multistream_config(R, O):
+    """Seed 42, 2^20 streams (counters 0..2^20-1) x 4 words, u32 and f32
+    uniform: compared in full."""
+    for dist in (0, 1):
+        out = R.fill_multi(0, dist, 42, 0, 1 << 20, 0, 4)
+        torch.cuda.synchronize()
+        ref = O.fill_multi(0, dist, 42, 0, 1 << 20, 0, 4)
+        assert np.array_equal(as_u32(out), bits(ref))
+
+
+@pytest.mark.parametrize("gen", GENS)
+@pytest.mark.parametrize("dist", DISTS)
+def test_fill_multi_parity(R, O, gen, dist):
+    for n_streams, off, per in [(1000, 0, 4), (333, 3, 9), (50, 100, 1000), (3, 0, 40000),
+                                (70, 16380, 70)]:
+        out = R.fill_multi(gen, dist, 1234, 2**32 - n_streams, n_streams, off, per)
+        torch.cuda.synchronize()
+        ref = O.fill_multi(gen, dist, 1234, 2**32 - n_streams, n_streams, off, per)
+        assert np.array_equal(as_u32(out), bits(ref)), (n_streams, off, per)
+
+
+@pytest.mark.parametrize("gen", [0, 3, 4])
+def test_launch_geometry_invariance(R, O, gen):
+    """Results do not depend on workgroup size, span length, grid size or
+    store kind (paper section 4: unique streams regardless of thread count)."""
+    n, off = 5 * 16384 + 11, 9
+    ref = bits(O.fill(gen, 2, 77, 8, off, n))
+    try:
+        for wg, un, mx, nt in [(64, 1, 1, 2), (128, 2, 3, 1), (256, 4, 0, 1), (512, 16, 7, 2),
+                               (192, 64, 0, 2), (320, 3, 2, 1)]:
+            R.orng_set_launch(wg, un, mx, nt)
+            out = R.fill(gen, 2, 77, 8, off, n)
+            torch.cuda.synchronize()
+            assert np.array_equal(as_u32(out), ref), (wg, un, mx, nt)
+    finally:
+        R.orng_reset_launch()
+
+
+def test_bulk_config_sampled(R, O):
+    """2^30 samples per generator and distribution, single stream, seed from
+    PCG64: sampled positions against the oracle, plus chunk invariance."""
+    from paper_2310_19925_amd import inputs
+    seed = inputs.bulk_seed()
+    n = inputs.BULK_N
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    rng = np.random.default_rng(7)
+    pos = np.concatenate([rng.integers(0, n, 3000), [0, 1, 2, 3, n - 4, n - 3, n - 2, n - 1],
+                          16384 * np.arange(1, 40)]).astype(np.int64)
+    idx = torch.from_numpy(pos).cuda()
+    for gen in GENS:
+        for dist in DISTS:
+            print("bulk gen=%d dist=%d" % (gen, dist), flush=True)
+            R.orng_fill(gen, dist, seed, 0, 0, n, out)
+            got = as_u32(out[idx])
+            ref = bits(O.samples_at(gen, dist, seed, np.zeros(pos.size, np.uint32), pos))
+            assert np.array_equal(got, ref), (gen, dist)
+            # a chunk starting at an odd offset equals the matching slice
+            part = R.fill(gen, dist, seed, 0, 12345677, 1 << 20)
+            assert torch.equal(part, out[12345677:12345677 + (1 << 20)])
+            if dist == 1:
+                f = out.view(torch.float32)
+                assert float(f.min()) >= 0.0 and float(f.max()) < 1.0
+            if dist == 2:
+                f = out.view(torch.float32)[: 1 << 26].double()
+                assert abs(float(f.mean())) < 5 / 2**13 and abs(float(f.var()) - 1) < 5 * 2**-12.5
+    del out
+    torch.cuda.empty_cache()
