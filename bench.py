@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the counter-based generation hot path on one MI355X.
+
+One step = one bulk fill of 2^30 samples for every generator (Philox4x32-10,
+Threefry4x32-20, Threefry2x64-20, Squares32, Tyche) and every distribution
+(u32, f32 uniform, f32 Box-Muller normal): 15 launches, 60 GiB written,
+single stream (seed from PCG64(231019925), counter 0) counter-partitioned
+across the grid.  `value` is whole-step throughput in GSamples/s with the
+output resident in HBM.  Per-kernel durations come from HIP events recorded on
+the launch stream around every launch of the timed steps.
+
+Also reported (same JSON line): the fused Brownian walk (2^24 particles, 3-D,
+10^4 steps) in steps/s, and the CPU oracle on a bounded sample of the same
+fill workload as the CPU baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-walk] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # full-rate 32-bit VALU lane-ops/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(seed, target_s=15.0):
+    """Oracle (test infrastructure, untuned) on the host cores: the same 15
+    fills on a bounded sample of each, scaled to GSamples/s."""
+    import numpy as np
+    from oracle import oracle as O
+    th = cpu_threads()
+    per = 1 << 20
+    t0 = time.perf_counter()
+    for g in range(5):
+        for d in range(3):
+            O.fill(g, d, seed, 0, 0, per, nthreads=th)
+    t_small = time.perf_counter() - t0
+    scale = max(1, min(256, int(target_s / max(t_small, 1e-3))))
+    per = per * scale
+    buf_u = np.empty(per, np.uint32)
+    t0 = time.perf_counter()
+    for g in range(5):
+        for d in range(3):
+            out = buf_u if d == 0 else buf_u.view(np.float32)
+            rc = O.lib().oracle_fill(g, d, seed, 0, 0, per, out.ctypes.data, th)
+            assert rc == 0
+    dt = time.perf_counter() - t0
+    return {"value": round(15 * per / dt / 1e9, 4), "unit": "GSamples/s", "cores": th,
+            "kind": "oracle",
+            "sample": "first %d samples of each of the 15 fills (gen x dist), %.1f s wall"
+                      % (per, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-walk", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", default="", help="gen:dist list to restrict the fills (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the generation path needs no communication "
+              "and this build runs on a single MI355X (--gpus %d refused)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2310_19925_amd import inputs, orng
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    seed = inputs.bulk_seed()
+    n = inputs.BULK_N
+    combos = [(g, d) for g in range(5) for d in range(3)]
+    if args.only:
+        keep = {tuple(int(x) for x in s.split(":")) for s in args.only.split(",")}
+        combos = [c for c in combos if c in keep]
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def step(events=None):
+        for k, (g, d) in enumerate(combos):
+            if events is not None:
+                events[k][0].record(stream)
+            orng.orng_fill(g, d, seed, 0, 0, n, out, stream)
+            if events is not None:
+                events[k][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in combos] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_kernel_ms = [sum(evs[s][k][0].elapsed_time(evs[s][k][1]) for s in range(args.steps))
+                     / args.steps for k in range(len(combos))]
+    total_samples = len(combos) * n * args.steps
+    value = total_samples / wall / 1e9
+    ms_per_step = wall / args.steps * 1e3
+
+    kernels = []
+    for (g, d), ms in zip(combos, per_kernel_ms):
+        gbs = 4.0 * n / (ms * 1e-3) / 1e9
+        kernels.append({"gen": inputs.GEN_NAMES[g], "dist": inputs.DIST_NAMES[d],
+                        "ms": round(ms, 4), "gsamples_s": round(n / (ms * 1e-3) / 1e9, 2),
+                        "write_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+    dom = max(range(len(combos)), key=lambda k: per_kernel_ms[k])
+    dk = kernels[dom]
+    roofline = {"bound": "hbm", "achieved": dk["write_gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": dk["hbm_frac"], "traffic": None,
+                "kernel": "%s/%s" % (dk["gen"], dk["dist"])}
+    total_ms = sum(per_kernel_ms)
+    step_hbm_frac = (4.0 * n * len(combos) / (total_ms * 1e-3) / 1e9) / HBM_PEAK_GBS
+
+    result = {
+        "metric": "GSamples/s + % HBM write BW (fill), steps/s (walk); batched/served vs plain",
+        "value": round(value, 3), "unit": "GSamples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32,f32", "data": "synthetic",
+        "config": {"workload": "bulk fill: 5 generators x {u32, f32 uniform, f32 normal}, "
+                               "2^30 samples each, single stream (seed PCG64(231019925), ctr 0)",
+                   "samples_per_fill": n, "fills_per_step": len(combos),
+                   "parallelism": "single GPU"},
+        "hbm_write_frac_step": round(step_hbm_frac, 4),
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+    del out
+    torch.cuda.empty_cache()
+
+    if not args.no_walk:
+        w = inputs.WALK
+        pos = torch.zeros((w["dim"], w["n_particles"]), dtype=torch.float32, device=dev)
+        msd = torch.zeros(w["n_steps"] // w["msd_every"], dtype=torch.float64, device=dev)
+        orng.orng_brownian(seed, 0, w["n_particles"], w["dim"], 0, 100, w["dt"], w["D"], pos,
+                           None, 0, stream)  # warm-up launch
+        pos.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        orng.orng_brownian(seed, 0, w["n_particles"], w["dim"], 0, w["n_steps"], w["dt"], w["D"],
+                           pos, msd, w["msd_every"], stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        m = (msd.cpu().numpy() / w["n_particles"]).tolist()
+        result["walk"] = {"steps_per_s": round(w["n_steps"] / (ms * 1e-3), 1),
+                          "particle_steps_per_s": round(w["n_steps"] * w["n_particles"]
+                                                        / (ms * 1e-3), 1),
+                          "ms": round(ms, 3), "n_particles": w["n_particles"], "dim": w["dim"],
+                          "n_steps": w["n_steps"],
+                          "msd_last": round(m[-1], 5),
+                          "msd_expected_last": 2 * w["dim"] * w["D"] * w["n_steps"] * w["dt"]}
+        del pos, msd
+
+    if not args.no_cpu:
+        log("cpu baseline ...")
+        result["cpu_baseline"] = cpu_baseline(seed)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

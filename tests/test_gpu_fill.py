@@ -157,7 +157,7 @@ def test_bulk_config_sampled(R, O):
             ref = bits(O.samples_at(gen, dist, seed, np.zeros(pos.size, np.uint32), pos))
             assert np.array_equal(got, ref), (gen, dist)
             # a chunk starting at an odd offset equals the matching slice
-            part = R.fill(gen, dist, seed, 0, 12345677, 1 << 20)
+            part = R.fill(gen, dist, seed, 0, 12345677, 1 << 20).view(torch.int32)
             assert torch.equal(part, out[12345677:12345677 + (1 << 20)])
             if dist == 1:
                 f = out.view(torch.float32)
