@@ -70,6 +70,47 @@ def cpu_baseline(seed, target_s=15.0):
                       % (per, dt)}
 
 
+def _time_events(stream, fn, reps):
+    import torch
+    fn()  # warm-up
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    ms.sort()
+    return ms[len(ms) // 2]
+
+
+def bench_batched(orng, inputs, stream, dev):
+    """10^5 Philox u32 streams of log-uniform length in [1, 2^20] words, packed
+    back to back: batched (one persistent launch) vs one launch per stream vs
+    one plain fill of the same number of words."""
+    import torch
+    b = inputs.batched_requests()
+    total = int(b["out_off"][-1])
+    buf = torch.empty(total, dtype=torch.int32, device=dev)
+    reqs = orng.make_requests(0, 0, b["seed"], b["ctr"], b["offset"], b["n"],
+                              buf.data_ptr() + 4 * b["out_off"][:-1])
+    t_batched = _time_events(stream, lambda: orng.orng_fill_batched(reqs, stream), 5)
+    t_each = _time_events(stream, lambda: orng.orng_fill_each(reqs, stream), 2)
+    half = total // 2
+    t_plain = _time_events(stream, lambda: orng.orng_fill_multi(0, 0, 42, 0, 2, 0, half, buf,
+                                                                 stream), 5)
+    del buf
+    torch.cuda.empty_cache()
+    g = lambda ms, words: round(words / (ms * 1e-3) / 1e9, 2)
+    return {"requests": int(b["n"].size), "words": total,
+            "batched_ms": round(t_batched, 3), "batched_gsamples_s": g(t_batched, total),
+            "each_ms": round(t_each, 3), "each_gsamples_s": g(t_each, total),
+            "plain_ms": round(t_plain, 3), "plain_gsamples_s": g(t_plain, 2 * half),
+            "batched_vs_plain": round(t_plain / t_batched * total / (2 * half), 4),
+            "batched_vs_each": round(t_each / t_batched, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +118,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-walk", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--only", default="", help="gen:dist list to restrict the fills (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -177,6 +219,9 @@ def main():
                           "msd_last": round(m[-1], 5),
                           "msd_expected_last": 2 * w["dim"] * w["D"] * w["n_steps"] * w["dt"]}
         del pos, msd
+
+    if not args.no_batched:
+        result["batched"] = bench_batched(orng, inputs, stream, dev)
 
     if not args.no_cpu:
         log("cpu baseline ...")

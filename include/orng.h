@@ -117,6 +117,55 @@ int orng_brownian(uint64_t seed, uint32_t ctr0, uint32_t n_particles, uint32_t d
                   uint64_t step0, uint32_t n_steps, float dt, float D, float *d_pos,
                   double *d_msd, uint32_t msd_every, void *stream);
 
+/*
+ * Fill request: the arguments of one orng_fill, as a record.  48 bytes.
+ *   out   : device buffer of n * 4 bytes (caller-owned, 4-byte aligned)
+ *   flags : reserved, must be 0
+ */
+typedef struct {
+    uint64_t seed;
+    uint64_t offset;
+    uint64_t n;
+    void *out;
+    uint32_t ctr;
+    uint32_t gen;
+    uint32_t dist;
+    uint32_t flags;
+} orng_req_t;
+
+/*
+ * orng_fill_batched -- every request r of h_reqs[0 .. nreq) is filled exactly
+ * as orng_fill(r.gen, r.dist, r.seed, r.ctr, r.offset, r.n, r.out) would fill
+ * it (each sample depends only on its own stream and position, section 3.1),
+ * in one persistent launch that pulls fixed-size tiles of all requests from a
+ * device work queue; the launch is replayed from a captured hipGraph.
+ * h_reqs is host memory, copied before the call returns.  Output ranges of
+ * different requests must not overlap.  Requests with n == 0 are skipped.
+ * Errors: EINVAL / ERANGE as orng_fill for the first bad request (nothing is
+ *         enqueued then); ENOMEM if the batch needs more than 2^28 tiles.
+ */
+int orng_fill_batched(const orng_req_t *h_reqs, size_t nreq, void *stream);
+
+/*
+ * orng_fill_each -- the plain path for the same request list: one fill launch
+ * per request, in order (the baseline the batched and served paths are
+ * compared with).  Same results and errors as orng_fill_batched.
+ */
+int orng_fill_each(const orng_req_t *h_reqs, size_t nreq, void *stream);
+
+/*
+ * orng_autotune -- time launch variants of the fill and batched kernels for
+ * (gen, dist) on the current device (workgroup size, blocks of four words per
+ * lane per tile, tiles per queue claim, persistent workgroups per CU) and keep
+ * the fastest; results never change, only speed.  Allocates about 1 GiB of
+ * device memory for the duration of the call and synchronizes the device.
+ * cache_path (nullable): text file that receives the table of tuned entries
+ * (existing entries for other pairs are kept).  orng_tune_load reads such a
+ * file; the library also reads $ORNG_TUNE_CACHE at first use.
+ */
+int orng_autotune(int gen, int dist, const char *cache_path);
+int orng_tune_load(const char *cache_path);
+
 /* Launch knobs for the fill kernels (0 = automatic).  They change speed
    only, never results.  Process-wide; NULL restores the defaults. */
 typedef struct {

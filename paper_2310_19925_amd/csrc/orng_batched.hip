@@ -1,0 +1,329 @@
+// Batched fills: many streams of uneven lengths in one persistent launch.
+//
+// Every request's output equals orng_fill of the same (gen, dist, seed, ctr,
+// offset, n) exactly: a sample depends only on its own stream and position
+// (paper section 3.1), never on the other requests of the batch.
+//
+// Host: requests are validated, each is cut into tiles (the span of the fill
+// kernels: 64*U blocks of four words, or one Tyche tile), and a prefix sum
+// gives every request its first tile number.  The header, the request table
+// and a tile -> request map are written into pinned staging and uploaded with
+// two copies into a device buffer whose layout is fixed for its capacity.
+// Device: a persistent grid pulls tiles from an atomic cursor in the header
+// (`chunk` tiles per pull), looks up the request of each tile in the map and
+// generates it with the same span code as the plain fill.  The launch is
+// captured once into a hipGraph per (buffer, launch shape) and replayed.
+// A small ring of such contexts per device lets consecutive calls overlap:
+// a context is reused only after the event of its previous launch.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/orng.h"
+#include "orng_internal.hpp"
+#include "orng_span.hpp"
+
+namespace orng {
+
+struct DevReq {             // 64 bytes, read by the kernel with scalar loads
+    char *out;
+    uint64_t p0, n, seed;
+    uint64_t first_span;    // absolute span number of the request's first tile
+    uint64_t tile_start;    // number of the request's first tile in the batch
+    uint32_t ctr;
+    uint32_t unroll;        // blocks per lane per tile (counter generators)
+    uint32_t flags;         // gen | dist << 4 | aligned << 8
+    uint32_t pad;
+};
+static_assert(sizeof(DevReq) == 64, "DevReq layout");
+
+struct BatchHdr {           // 64 bytes
+    uint64_t total_tiles;
+    uint64_t cursor;        // next unclaimed tile; uploaded as 0 with the header
+    uint32_t nreq;
+    uint32_t chunk;
+    uint64_t pad[5];
+};
+static_assert(sizeof(BatchHdr) == 64, "BatchHdr layout");
+
+struct BatchView {
+    BatchHdr *hdr;
+    const DevReq *reqs;
+    const uint32_t *map;
+};
+
+__device__ __forceinline__ uint64_t bcast_lane0(uint64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Generate tile t of the batch (wave-uniform t).
+template <bool NT>
+__device__ __forceinline__ void run_tile(const DevReq *reqs, const uint32_t *map, uint64_t t,
+                                         uint32_t lane) {
+    const uint32_t r = map[t];
+    const DevReq q = reqs[r];
+    const uint64_t span = q.first_span + (t - q.tile_start);
+    const KeySched ks = make_keysched(q.seed);
+    const int gen = (int)(q.flags & 15u), dist = (int)((q.flags >> 4) & 15u);
+    process_span_any<NT>(gen, dist, ks, q.ctr, q.out, q.p0, q.p0 + q.n, span, q.unroll,
+                         (q.flags >> 8) & 1u, lane);
+}
+
+template <bool NT>
+__global__ __launch_bounds__(512) void k_batched(BatchView v) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t total = v.hdr->total_tiles;
+    const uint32_t chunk = v.hdr->chunk;
+    for (;;) {
+        uint64_t t0 = 0;
+        if (lane == 0)
+            t0 = atomicAdd(reinterpret_cast<unsigned long long *>(&v.hdr->cursor),
+                           (unsigned long long)chunk);
+        t0 = bcast_lane0(t0);
+        if (t0 >= total) break;
+        const uint64_t t1 = t0 + chunk < total ? t0 + chunk : total;
+        for (uint64_t t = t0; t < t1; ++t) run_tile<NT>(v.reqs, v.map, t, lane);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct BatchCtx {
+    char *d_buf = nullptr;
+    char *h_buf = nullptr;  // pinned staging, same layout
+    uint64_t cap_req = 0, cap_tiles = 0;
+    hipEvent_t done = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t graph_key[4] = {0, 0, 0, 0};
+};
+
+struct DeviceBatch {
+    std::mutex mu;
+    std::vector<BatchCtx> ring;
+    size_t next = 0;
+    hipStream_t capture = nullptr;
+};
+
+static std::mutex g_dev_mu;
+static std::vector<DeviceBatch *> g_devs;
+
+static DeviceBatch *device_batch(int dev) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if ((int)g_devs.size() <= dev) g_devs.resize(dev + 1, nullptr);
+    if (!g_devs[dev]) {
+        g_devs[dev] = new DeviceBatch();  // lives until process exit
+        g_devs[dev]->ring.resize(3);
+    }
+    return g_devs[dev];
+}
+
+static size_t layout_bytes(uint64_t cap_req, uint64_t cap_tiles, size_t *map_off) {
+    const size_t off = sizeof(BatchHdr) + cap_req * sizeof(DevReq);
+    *map_off = off;
+    return off + cap_tiles * sizeof(uint32_t);
+}
+
+static hipError_t ensure_capacity(BatchCtx &c, uint64_t nreq, uint64_t tiles) {
+    if (nreq <= c.cap_req && tiles <= c.cap_tiles && c.d_buf) return hipSuccess;
+    const uint64_t nr = std::max<uint64_t>(std::max<uint64_t>(nreq, c.cap_req * 3 / 2), 1024);
+    const uint64_t nt = std::max<uint64_t>(std::max<uint64_t>(tiles, c.cap_tiles * 3 / 2), 65536);
+    size_t map_off;
+    const size_t bytes = layout_bytes(nr, nt, &map_off);
+    hipError_t e;
+    if (c.exec) { hipGraphExecDestroy(c.exec); c.exec = nullptr; }
+    if (c.graph) { hipGraphDestroy(c.graph); c.graph = nullptr; }
+    if (c.d_buf) { hipFree(c.d_buf); c.d_buf = nullptr; }
+    if (c.h_buf) { hipHostFree(c.h_buf); c.h_buf = nullptr; }
+    c.cap_req = c.cap_tiles = 0;
+    if ((e = hipMalloc(&c.d_buf, bytes)) != hipSuccess) return e;
+    if ((e = hipHostMalloc(&c.h_buf, bytes, hipHostMallocDefault)) != hipSuccess) return e;
+    c.cap_req = nr;
+    c.cap_tiles = nt;
+    return hipSuccess;
+}
+
+// Launch shape shared by the batched and served kernels.
+struct BatchShape {
+    uint32_t wg, grid, chunk;
+    bool nt;
+};
+
+static BatchShape batch_shape(int gen, int dist, uint64_t tiles) {
+    const Tuned tu = tuned_fill(gen, dist);
+    const LaunchCfg cfg = launch_cfg();
+    BatchShape s;
+    s.wg = cfg.wg_size ? cfg.wg_size : tu.b_wg_size;
+    s.chunk = tu.b_chunk ? tu.b_chunk : 1;
+    uint64_t grid = (uint64_t)device_cu_count() * (tu.b_wgs_per_cu ? tu.b_wgs_per_cu : 8);
+    if (cfg.max_wgs) grid = cfg.max_wgs;
+    const uint64_t need = (tiles + (s.wg / 64) - 1) / (s.wg / 64);
+    s.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(grid, need));
+    s.nt = false;
+    return s;
+}
+
+static void *batched_kernel(bool nt) {
+    return nt ? reinterpret_cast<void *>(&k_batched<true>)
+              : reinterpret_cast<void *>(&k_batched<false>);
+}
+
+int validate_request(const orng_req_t &r) {
+    if (r.gen > ORNG_TYCHE || r.dist > ORNG_F32_NORMAL || r.flags != 0) return ORNG_EINVAL;
+    if (r.offset > PERIOD || r.n > PERIOD - r.offset) return ORNG_ERANGE;
+    if (r.n == 0) return ORNG_OK;
+    if (!r.out || (reinterpret_cast<uintptr_t>(r.out) & 3u)) return ORNG_EINVAL;
+    return ORNG_OK;
+}
+
+// Tile decomposition of one request with `unroll` blocks per lane.
+static void request_tiles(const orng_req_t &r, uint32_t unroll, uint64_t *first_span,
+                          uint64_t *count) {
+    const uint64_t sb = span_blocks((int)r.gen, unroll);
+    const uint64_t fb = r.offset / 4, lb = (r.offset + r.n - 1) / 4;
+    *first_span = fb / sb;
+    *count = lb / sb - *first_span + 1;
+}
+
+static bool use_graphs() {
+    static const bool on = [] {
+        const char *e = getenv("ORNG_NO_GRAPH");
+        return !(e && *e && *e != '0');
+    }();
+    return on;
+}
+
+int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
+    if (nreq && !reqs) return ORNG_EINVAL;
+    for (size_t i = 0; i < nreq; ++i) {
+        const int st = validate_request(reqs[i]);
+        if (st != ORNG_OK) return st;
+    }
+    // requests with work, tile counts and prefix
+    std::vector<uint32_t> live;
+    live.reserve(nreq);
+    for (size_t i = 0; i < nreq; ++i)
+        if (reqs[i].n) live.push_back((uint32_t)i);
+    if (live.empty()) return ORNG_OK;
+    std::vector<uint64_t> fspan(live.size()), cnt(live.size());
+    std::vector<uint32_t> unr(live.size());
+    uint64_t tiles = 0;
+    for (size_t k = 0; k < live.size(); ++k) {
+        const orng_req_t &r = reqs[live[k]];
+        unr[k] = r.gen == ORNG_TYCHE ? 64 : tuned_fill((int)r.gen, (int)r.dist).b_unroll;
+        request_tiles(r, unr[k], &fspan[k], &cnt[k]);
+        tiles += cnt[k];
+    }
+    if (tiles > (1ull << 28)) return ORNG_ENOMEM;
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; }
+    DeviceBatch *db = device_batch(dev);
+    std::lock_guard<std::mutex> lk(db->mu);
+    BatchCtx &c = db->ring[db->next];
+    db->next = (db->next + 1) % db->ring.size();
+#define ORNG_TRY(x) do { e = (x); if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; } } while (0)
+    if (!c.done) ORNG_TRY(hipEventCreateWithFlags(&c.done, hipEventDisableTiming));
+    else ORNG_TRY(hipEventSynchronize(c.done));  // staging and tables of its last use are free
+    ORNG_TRY(ensure_capacity(c, live.size(), tiles));
+    if (!db->capture) ORNG_TRY(hipStreamCreateWithFlags(&db->capture, hipStreamNonBlocking));
+
+    const orng_req_t &r0 = reqs[live[0]];
+    const BatchShape sh = batch_shape((int)r0.gen, (int)r0.dist, tiles);
+    size_t map_off;
+    layout_bytes(c.cap_req, c.cap_tiles, &map_off);
+    BatchHdr *hdr = reinterpret_cast<BatchHdr *>(c.h_buf);
+    DevReq *dq = reinterpret_cast<DevReq *>(c.h_buf + sizeof(BatchHdr));
+    uint32_t *map = reinterpret_cast<uint32_t *>(c.h_buf + map_off);
+    std::memset(hdr, 0, sizeof(BatchHdr));
+    hdr->total_tiles = tiles;
+    hdr->cursor = 0;
+    hdr->nreq = (uint32_t)live.size();
+    hdr->chunk = sh.chunk;
+    uint64_t ts = 0;
+    for (size_t k = 0; k < live.size(); ++k) {
+        const orng_req_t &r = reqs[live[k]];
+        DevReq &d = dq[k];
+        d.out = static_cast<char *>(r.out);
+        d.p0 = r.offset;
+        d.n = r.n;
+        d.seed = r.seed;
+        d.first_span = fspan[k];
+        d.tile_start = ts;
+        d.ctr = r.ctr;
+        d.unroll = unr[k];
+        const uint64_t addr_words = reinterpret_cast<uintptr_t>(r.out) / 4;
+        const uint32_t aligned = ((addr_words - r.offset) & 3u) == 0;
+        d.flags = r.gen | (r.dist << 4) | (aligned << 8);
+        d.pad = 0;
+        for (uint64_t t = 0; t < cnt[k]; ++t) map[ts + t] = (uint32_t)k;
+        ts += cnt[k];
+    }
+    ORNG_TRY(hipMemcpyAsync(c.d_buf, c.h_buf, sizeof(BatchHdr) + live.size() * sizeof(DevReq),
+                            hipMemcpyHostToDevice, stream));
+    ORNG_TRY(hipMemcpyAsync(c.d_buf + map_off, c.h_buf + map_off, tiles * sizeof(uint32_t),
+                            hipMemcpyHostToDevice, stream));
+
+    BatchView v;
+    v.hdr = reinterpret_cast<BatchHdr *>(c.d_buf);
+    v.reqs = reinterpret_cast<const DevReq *>(c.d_buf + sizeof(BatchHdr));
+    v.map = reinterpret_cast<const uint32_t *>(c.d_buf + map_off);
+    void *args[] = {&v};
+    if (use_graphs()) {
+        const uint64_t key[4] = {reinterpret_cast<uintptr_t>(c.d_buf), sh.wg, sh.grid,
+                                 (uint64_t)sh.nt};
+        if (!c.exec || std::memcmp(key, c.graph_key, sizeof key) != 0) {
+            if (c.exec) { hipGraphExecDestroy(c.exec); c.exec = nullptr; }
+            if (c.graph) { hipGraphDestroy(c.graph); c.graph = nullptr; }
+            ORNG_TRY(hipStreamBeginCapture(db->capture, hipStreamCaptureModeThreadLocal));
+            hipError_t le = hipLaunchKernel(batched_kernel(sh.nt), dim3(sh.grid), dim3(sh.wg),
+                                            args, 0, db->capture);
+            hipError_t ce = hipStreamEndCapture(db->capture, &c.graph);
+            ORNG_TRY(le);
+            ORNG_TRY(ce);
+            ORNG_TRY(hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0));
+            std::memcpy(c.graph_key, key, sizeof key);
+        }
+        ORNG_TRY(hipGraphLaunch(c.exec, stream));
+    } else {
+        ORNG_TRY(hipLaunchKernel(batched_kernel(sh.nt), dim3(sh.grid), dim3(sh.wg), args, 0,
+                                 stream));
+    }
+    ORNG_TRY(hipEventRecord(c.done, stream));
+#undef ORNG_TRY
+    return ORNG_OK;
+}
+
+}  // namespace orng
+
+extern "C" {
+
+int orng_fill_batched(const orng_req_t *h_reqs, size_t nreq, void *stream) {
+    return orng::fill_batched(h_reqs, nreq, static_cast<hipStream_t>(stream));
+}
+
+int orng_fill_each(const orng_req_t *h_reqs, size_t nreq, void *stream) {
+    if (nreq && !h_reqs) return ORNG_EINVAL;
+    for (size_t i = 0; i < nreq; ++i) {
+        const int st = orng::validate_request(h_reqs[i]);
+        if (st != ORNG_OK) return st;
+    }
+    for (size_t i = 0; i < nreq; ++i) {
+        const orng_req_t &r = h_reqs[i];
+        if (!r.n) continue;
+        hipError_t e = orng::launch_fill((int)r.gen, (int)r.dist, r.seed, r.ctr, 1, r.offset, r.n,
+                                         r.out, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) {
+            orng::set_hip_error(e);
+            return ORNG_EHIP;
+        }
+    }
+    return ORNG_OK;
+}
+
+}  // extern "C"

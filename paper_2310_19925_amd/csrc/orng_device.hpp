@@ -200,6 +200,35 @@ struct Tyche {
     }
 };
 
+// Key material for a seed.  Host and device: the batched and served kernels
+// build it per request with scalar instructions.
+__host__ __device__ inline KeySched make_keysched(uint64_t seed) {
+    KeySched k{};
+    k.seed_lo = (uint32_t)seed;
+    k.seed_hi = (uint32_t)(seed >> 32);
+    uint32_t k0 = k.seed_lo, k1 = k.seed_hi;
+    for (int r = 0; r < 10; ++r) {
+        k.k[r][0] = k0;
+        k.k[r][1] = k1;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    k.ks4[0] = k.seed_lo;
+    k.ks4[1] = k.seed_hi;
+    k.ks4[2] = 0u;
+    k.ks4[3] = 0u;
+    k.ks4[4] = 0x1BD11BDAu ^ k.seed_lo ^ k.seed_hi;
+    k.ks2[0] = seed;
+    k.ks2[1] = 0ull;
+    k.ks2[2] = 0x1BD11BDAA9FC1A22ull ^ seed;
+    // Squares key: one SplitMix64 output step of the seed, low bit forced on
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    k.sqkey = (z ^ (z >> 31)) | 1ull;
+    return k;
+}
+
 constexpr uint32_t TYCHE_TILE_WORDS = 16384;
 constexpr uint32_t TYCHE_TILE_BLOCKS = 4096;
 

@@ -17,35 +17,9 @@
 // end of the range, and any output whose address is not 16-byte aligned with
 // respect to the block grid, are written one dword at a time.
 #include "orng_internal.hpp"
+#include "orng_span.hpp"
 
 namespace orng {
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-template <bool NT>
-__device__ __forceinline__ void store16(char *p, const uint32_t w[4]) {
-    u32x4 v = {w[0], w[1], w[2], w[3]};
-    if constexpr (NT)
-        __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
-    else
-        *reinterpret_cast<u32x4 *>(p) = v;
-}
-
-// Store block with first position p into base[pos - p0] for pos in [p0, pend).
-template <bool NT>
-__device__ __forceinline__ void store_block(char *base, uint64_t p, uint64_t p0, uint64_t pend,
-                                            bool aligned, const uint32_t w[4]) {
-    if (aligned && p >= p0 && p + 4 <= pend) {
-        store16<NT>(base + 4 * (p - p0), w);
-        return;
-    }
-    uint32_t *o = reinterpret_cast<uint32_t *>(base);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint64_t q = p + (uint64_t)i;
-        if (q >= p0 && q < pend) o[q - p0] = w[i];
-    }
-}
 
 struct SpanArgs {
     KeySched ks;
@@ -59,10 +33,6 @@ struct SpanArgs {
     uint32_t unroll;           // U (counter generators)
     uint32_t aligned;          // 16-byte stores are legal
 };
-
-__device__ __forceinline__ uint32_t wave_uniform(uint32_t v) {
-    return __builtin_amdgcn_readfirstlane(v);
-}
 
 template <int G, int D, bool NT>
 __global__ __launch_bounds__(512) void k_span(SpanArgs a) {
@@ -80,32 +50,7 @@ __global__ __launch_bounds__(512) void k_span(SpanArgs a) {
         const uint64_t span = a.first_span + sl;
         const uint32_t ctr = a.ctr0 + (uint32_t)si;
         char *base = a.out + si * a.n * 4;
-        if constexpr (G == G_TYCHE) {
-            Tyche st;
-            st.seed(a.ks, (uint32_t)span * 64u + lane, ctr);
-            const uint64_t tile_block = span * TYCHE_TILE_BLOCKS;
-            for (uint32_t k = 0; k < 64; ++k) {
-                const uint64_t bw = tile_block + 64u * k;
-                if (bw * 4 >= pend) break;
-                uint32_t w[4];
-                st.next4(w);
-                const uint64_t p = (bw + lane) * 4;
-                if (p + 4 <= a.p0) continue;
-                convert4<D>(w);
-                store_block<NT>(base, p, a.p0, pend, a.aligned, w);
-            }
-        } else {
-            const uint64_t b0 = span * 64u * a.unroll;
-            for (uint32_t u = 0; u < a.unroll; ++u) {
-                const uint64_t bw = b0 + 64u * u;
-                if (bw * 4 >= pend) break;
-                const uint64_t b = bw + lane;
-                uint32_t w[4];
-                counter_block<G>((uint32_t)b, ctr, a.ks, w);
-                convert4<D>(w);
-                store_block<NT>(base, b * 4, a.p0, pend, a.aligned, w);
-            }
-        }
+        process_span<G, D, NT>(a.ks, ctr, base, a.p0, pend, span, a.unroll, a.aligned, lane);
     }
 }
 
@@ -177,38 +122,11 @@ static void *pick_kernel(int gen, int dist, bool units, bool nt) {
     }
 }
 
-KeySched make_keysched(uint64_t seed) {
-    KeySched k{};
-    k.seed_lo = (uint32_t)seed;
-    k.seed_hi = (uint32_t)(seed >> 32);
-    uint32_t k0 = k.seed_lo, k1 = k.seed_hi;
-    for (int r = 0; r < 10; ++r) {
-        k.k[r][0] = k0;
-        k.k[r][1] = k1;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    k.ks4[0] = k.seed_lo;
-    k.ks4[1] = k.seed_hi;
-    k.ks4[2] = 0u;
-    k.ks4[3] = 0u;
-    k.ks4[4] = 0x1BD11BDAu ^ k.seed_lo ^ k.seed_hi;
-    k.ks2[0] = seed;
-    k.ks2[1] = 0ull;
-    k.ks2[2] = 0x1BD11BDAA9FC1A22ull ^ seed;
-    // Squares key: one SplitMix64 output step of the seed, low bit forced on
-    uint64_t z = seed + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    k.sqkey = (z ^ (z >> 31)) | 1ull;
-    return k;
-}
-
 hipError_t launch_fill(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t n_streams,
                        uint64_t offset, uint64_t per_stream, void *out, hipStream_t s) {
     if (n_streams == 0 || per_stream == 0) return hipSuccess;
     const LaunchCfg cfg = launch_cfg();
-    const bool nt = cfg.nontemporal == 1;
+    const bool nt = cfg.nontemporal ? cfg.nontemporal == 1 : tuned_fill(gen, dist).nontemporal == 1;
     const uint64_t addr_words = reinterpret_cast<uintptr_t>(out) / 4;
     const bool aligned = ((addr_words - offset) & 3u) == 0 && (n_streams == 1 || per_stream % 4 == 0);
     const uint64_t first_block = offset / 4;
@@ -240,21 +158,16 @@ hipError_t launch_fill(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t
     a.n = per_stream;
     a.ctr0 = ctr0;
     a.aligned = aligned;
-    uint64_t span_blocks;
-    if (gen == G_TYCHE) {
-        a.unroll = 64;
-        span_blocks = TYCHE_TILE_BLOCKS;
-    } else {
-        a.unroll = cfg.unroll ? cfg.unroll : 4;
-        span_blocks = 64ull * a.unroll;
-    }
-    a.first_span = first_block / span_blocks;
-    a.spans_per_stream = last_block / span_blocks - a.first_span + 1;
+    const Tuned tu = tuned_fill(gen, dist);
+    a.unroll = gen == G_TYCHE ? 64 : (cfg.unroll ? cfg.unroll : tu.unroll);
+    const uint64_t sb = span_blocks(gen, a.unroll);
+    a.first_span = first_block / sb;
+    a.spans_per_stream = last_block / sb - a.first_span + 1;
     a.total_spans = a.spans_per_stream * n_streams;
-    const uint32_t wg = cfg.wg_size ? cfg.wg_size : 256;
+    const uint32_t wg = cfg.wg_size ? cfg.wg_size : tu.wg_size;
     const uint64_t wpg = wg / 64;
     uint64_t grid = (a.total_spans + wpg - 1) / wpg;
-    const uint64_t cap = cfg.max_wgs ? cfg.max_wgs : (1ull << 30);
+    const uint64_t cap = cfg.max_wgs ? cfg.max_wgs : (tu.max_wgs ? tu.max_wgs : (1ull << 30));
     if (grid > cap) grid = cap;
     void *args[] = {&a};
     return hipLaunchKernel(pick_kernel(gen, dist, false, nt), dim3((uint32_t)grid), dim3(wg), args,

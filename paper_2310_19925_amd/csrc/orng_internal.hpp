@@ -20,7 +20,21 @@ struct LaunchCfg {
     uint32_t nontemporal;  // 1: nontemporal stores, 2: normal stores, 0: auto
 };
 
-KeySched make_keysched(uint64_t seed);
+// Tuned launch parameters of one (generator, distribution) pair.
+struct Tuned {
+    uint32_t wg_size;      // fill: threads per workgroup
+    uint32_t unroll;       // fill: blocks per lane per span
+    uint32_t max_wgs;      // fill: grid cap (0: one wave per span)
+    uint32_t nontemporal;  // fill: 1 nontemporal, 2 ordinary stores
+    uint32_t b_wg_size;    // batched: threads per workgroup
+    uint32_t b_unroll;     // batched: blocks per lane per tile
+    uint32_t b_chunk;      // batched: tiles claimed per queue access
+    uint32_t b_wgs_per_cu; // batched: persistent workgroups per CU
+};
+Tuned tuned_fill(int gen, int dist);
+void set_tuned(int gen, int dist, const Tuned &t);
+int load_tune_cache(const char *path);
+int save_tune_cache(const char *path);
 
 // Current launch configuration (thread-safe copy).
 LaunchCfg launch_cfg();

@@ -1,0 +1,266 @@
+// Launch-parameter table and the autotuner that fills it.
+//
+// Launch parameters change speed only: every output is a function of its
+// stream and position alone, so any workgroup size, span length, grid size,
+// queue claim size or store kind gives identical results.  The table starts
+// from defaults measured on MI355X and can be refined per (gen, dist) by
+// orng_autotune, which times variants on the current device and keeps the
+// fastest.  Entries persist in a small text file (one line per pair).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <random>
+#include <vector>
+
+#include "../../include/orng.h"
+#include "orng_internal.hpp"
+
+namespace orng {
+
+int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream);
+
+static std::mutex g_tune_mu;
+static Tuned g_tuned[5][3];
+static bool g_tuned_init = false;
+
+static Tuned default_tuned(int gen, int dist) {
+    Tuned t;
+    t.wg_size = 256;
+    t.unroll = (gen == G_TYCHE) ? 64 : 1;
+    t.max_wgs = 0;
+    t.nontemporal = 2;
+    t.b_wg_size = 256;
+    t.b_unroll = 16;
+    t.b_chunk = 1;
+    t.b_wgs_per_cu = 8;
+    (void)dist;
+    return t;
+}
+
+static void init_locked() {
+    if (g_tuned_init) return;
+    for (int g = 0; g < 5; ++g)
+        for (int d = 0; d < 3; ++d) g_tuned[g][d] = default_tuned(g, d);
+    g_tuned_init = true;
+}
+
+static int load_locked(const char *path);
+
+static void init_from_env_once() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char *p = getenv("ORNG_TUNE_CACHE");
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        init_locked();
+        if (p && *p) load_locked(p);
+    });
+}
+
+Tuned tuned_fill(int gen, int dist) {
+    init_from_env_once();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tuned[gen][dist];
+}
+
+void set_tuned(int gen, int dist, const Tuned &t) {
+    init_from_env_once();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[gen][dist] = t;
+}
+
+static bool sane(const Tuned &t, int gen) {
+    auto wg_ok = [](uint32_t w) { return w >= 64 && w <= 512 && w % 64 == 0; };
+    return wg_ok(t.wg_size) && wg_ok(t.b_wg_size) && t.unroll >= 1 && t.unroll <= 64 &&
+           t.b_unroll >= 1 && t.b_unroll <= 64 && t.b_chunk >= 1 && t.b_chunk <= 64 &&
+           t.b_wgs_per_cu >= 1 && t.b_wgs_per_cu <= 64 && t.nontemporal >= 1 &&
+           t.nontemporal <= 2 && (gen != G_TYCHE || t.unroll == 64);
+}
+
+static int load_locked(const char *path) {
+    FILE *f = fopen(path, "r");
+    if (!f) return ORNG_ENOENT;
+    char line[256];
+    int loaded = 0;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        int g, d;
+        Tuned t;
+        if (sscanf(line, "%d %d %u %u %u %u %u %u %u %u", &g, &d, &t.wg_size, &t.unroll,
+                   &t.max_wgs, &t.nontemporal, &t.b_wg_size, &t.b_unroll, &t.b_chunk,
+                   &t.b_wgs_per_cu) == 10 &&
+            g >= 0 && g < 5 && d >= 0 && d < 3 && sane(t, g)) {
+            g_tuned[g][d] = t;
+            ++loaded;
+        }
+    }
+    fclose(f);
+    return loaded > 0 ? ORNG_OK : ORNG_EINVAL;
+}
+
+int load_tune_cache(const char *path) {
+    init_from_env_once();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return load_locked(path);
+}
+
+int save_tune_cache(const char *path) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    init_locked();
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return ORNG_EINVAL;
+    fprintf(f, "# orng launch table: gen dist wg unroll max_wgs nontemporal "
+               "batched_wg batched_unroll batched_chunk batched_wgs_per_cu\n");
+    for (int g = 0; g < 5; ++g)
+        for (int d = 0; d < 3; ++d) {
+            const Tuned &t = g_tuned[g][d];
+            fprintf(f, "%d %d %u %u %u %u %u %u %u %u\n", g, d, t.wg_size, t.unroll, t.max_wgs,
+                    t.nontemporal, t.b_wg_size, t.b_unroll, t.b_chunk, t.b_wgs_per_cu);
+        }
+    fclose(f);
+    return rename(tmp.c_str(), path) == 0 ? ORNG_OK : ORNG_EINVAL;
+}
+
+// Median of `reps` timed runs of fn on stream s, in milliseconds.
+template <class F>
+static float time_ms(hipStream_t s, int reps, F fn, hipError_t *err) {
+    hipEvent_t a, b;
+    *err = hipEventCreate(&a);
+    if (*err != hipSuccess) return 0;
+    *err = hipEventCreate(&b);
+    if (*err != hipSuccess) { hipEventDestroy(a); return 0; }
+    std::vector<float> v;
+    fn();  // warm-up
+    for (int i = 0; i < reps && *err == hipSuccess; ++i) {
+        hipEventRecord(a, s);
+        fn();
+        hipEventRecord(b, s);
+        *err = hipEventSynchronize(b);
+        float ms = 0;
+        hipEventElapsedTime(&ms, a, b);
+        v.push_back(ms);
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (v.empty()) return 1e30f;
+    std::sort(v.begin(), v.end());
+    return v[v.size() / 2];
+}
+
+}  // namespace orng
+
+using namespace orng;
+
+extern "C" {
+
+int orng_tune_load(const char *cache_path) {
+    if (!cache_path) return ORNG_EINVAL;
+    return load_tune_cache(cache_path);
+}
+
+int orng_autotune(int gen, int dist, const char *cache_path) {
+    if (gen < 0 || gen > 4 || dist < 0 || dist > 2) return ORNG_EINVAL;
+    const uint64_t n = 1ull << 28;  // 1 GiB of samples
+    void *buf = nullptr;
+    hipStream_t s = nullptr;
+    hipError_t e = hipMalloc(&buf, n * 4);
+    if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; }
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) { hipFree(buf); set_hip_error(e); return ORNG_EHIP; }
+    const LaunchCfg saved_cfg = launch_cfg();
+    set_launch_cfg(LaunchCfg{0, 0, 0, 0});
+    Tuned best = tuned_fill(gen, dist);
+    const int cus = device_cu_count();
+
+    // plain fill: workgroup size x span length x grid cap x store kind
+    float best_ms = 1e30f;
+    const uint32_t wgs[] = {64, 128, 256, 512};
+    const uint32_t unrolls[] = {1, 2, 4, 8};
+    const uint32_t caps[] = {0, (uint32_t)cus * 8, (uint32_t)cus * 32};
+    for (uint32_t wg : wgs)
+        for (uint32_t un : unrolls) {
+            if (gen == G_TYCHE && un != 1) continue;
+            for (uint32_t cap : caps)
+                for (uint32_t nt = 1; nt <= 2 && e == hipSuccess; ++nt) {
+                    Tuned t = best;
+                    t.wg_size = wg;
+                    t.unroll = gen == G_TYCHE ? 64 : un;
+                    t.max_wgs = cap;
+                    t.nontemporal = nt;
+                    set_tuned(gen, dist, t);
+                    const float ms = time_ms(s, 3, [&] {
+                        launch_fill(gen, dist, 0x5EED, 0, 1, 0, n, buf, s);
+                    }, &e);
+                    if (ms < best_ms) { best_ms = ms; best.wg_size = wg; best.unroll = t.unroll;
+                                        best.max_wgs = cap; best.nontemporal = nt; }
+                }
+        }
+
+    // batched: uneven requests packed back to back
+    std::mt19937_64 rng(12345);
+    std::vector<orng_req_t> reqs;
+    uint64_t used = 0;
+    while (reqs.size() < 2048) {
+        const double u = std::uniform_real_distribution<double>(0.0, 20.0)(rng);
+        uint64_t len = (uint64_t)std::pow(2.0, u);
+        if (len < 1) len = 1;
+        if (used + len > n) break;
+        orng_req_t r;
+        r.seed = rng();
+        r.ctr = (uint32_t)rng();
+        r.offset = rng() % (PERIOD - len + 1);
+        r.n = len;
+        r.out = static_cast<char *>(buf) + used * 4;
+        r.gen = (uint32_t)gen;
+        r.dist = (uint32_t)dist;
+        r.flags = 0;
+        reqs.push_back(r);
+        used += len;
+    }
+    float best_b = 1e30f;
+    Tuned bt = best;
+    for (uint32_t wg : {256u, 512u})
+        for (uint32_t un : {4u, 8u, 16u, 32u})
+            for (uint32_t ch : {1u, 2u, 4u})
+                for (uint32_t wpc : {4u, 8u, 16u}) {
+                    if (e != hipSuccess) break;
+                    if (gen == G_TYCHE && un != 16) continue;
+                    Tuned t = best;
+                    t.b_wg_size = wg;
+                    t.b_unroll = un;
+                    t.b_chunk = ch;
+                    t.b_wgs_per_cu = wpc;
+                    set_tuned(gen, dist, t);
+                    int st = ORNG_OK;
+                    const float ms = time_ms(s, 3, [&] {
+                        st = fill_batched(reqs.data(), reqs.size(), s);
+                    }, &e);
+                    if (st != ORNG_OK) continue;
+                    if (ms < best_b) { best_b = ms; bt = t; }
+                }
+    best.b_wg_size = bt.b_wg_size;
+    best.b_unroll = bt.b_unroll;
+    best.b_chunk = bt.b_chunk;
+    best.b_wgs_per_cu = bt.b_wgs_per_cu;
+    set_tuned(gen, dist, best);
+    set_launch_cfg(saved_cfg);
+    hipError_t e2 = hipStreamSynchronize(s);
+    hipStreamDestroy(s);
+    hipFree(buf);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; }
+    if (cache_path) {
+        load_tune_cache(cache_path);  // keep other pairs already in the file...
+        set_tuned(gen, dist, best);   // ...but this pair's fresh result wins
+        return save_tune_cache(cache_path);
+    }
+    return ORNG_OK;
+}
+
+}  // extern "C"

@@ -44,6 +44,10 @@ def _load():
         "orng_fill": [i32, i32, u64, u32, u64, u64, vp, vp],
         "orng_fill_multi": [i32, i32, u64, u32, u32, u64, u64, vp, vp],
         "orng_brownian": [u64, u32, u32, u32, u64, u32, f32, f32, vp, vp, u32, vp],
+        "orng_fill_batched": [vp, C.c_size_t, vp],
+        "orng_fill_each": [vp, C.c_size_t, vp],
+        "orng_autotune": [i32, i32, C.c_char_p],
+        "orng_tune_load": [C.c_char_p],
         "orng_set_launch": [C.POINTER(orng_launch_t)],
         "orng_get_launch": [C.POINTER(orng_launch_t)],
         "orng_last_hip_error": [],
@@ -117,6 +121,50 @@ def orng_get_launch():
     _check(_lib.orng_get_launch(C.byref(cfg)), "orng_get_launch")
     return dict(wg_size=cfg.wg_size, unroll=cfg.unroll, max_wgs=cfg.max_wgs,
                 nontemporal=cfg.nontemporal)
+
+
+# orng_req_t as a numpy structured dtype (48 bytes, same field order)
+def _req_dtype():
+    import numpy as np
+    return np.dtype([("seed", "<u8"), ("offset", "<u8"), ("n", "<u8"), ("out", "<u8"),
+                     ("ctr", "<u4"), ("gen", "<u4"), ("dist", "<u4"), ("flags", "<u4")],
+                    align=False)
+
+
+def make_requests(gen, dist, seed, ctr, offset, n, out_ptr):
+    """Build a contiguous orng_req_t array from per-request sequences (or
+    scalars broadcast to the common length).  out_ptr: device addresses."""
+    import numpy as np
+    cols = [np.asarray(x) for x in (gen, dist, seed, ctr, offset, n, out_ptr)]
+    m = max(c.size for c in cols)
+    r = np.zeros(m, dtype=_req_dtype())
+    r["gen"], r["dist"] = cols[0], cols[1]
+    r["seed"], r["ctr"] = cols[2].astype(np.uint64), cols[3].astype(np.uint32)
+    r["offset"], r["n"] = cols[4].astype(np.uint64), cols[5].astype(np.uint64)
+    r["out"] = cols[6].astype(np.uint64)
+    return r
+
+
+def orng_fill_batched(reqs, stream=None):
+    """reqs: numpy array of dtype _req_dtype() (see make_requests)."""
+    assert reqs.dtype.itemsize == 48 and reqs.flags["C_CONTIGUOUS"]
+    _check(_lib.orng_fill_batched(reqs.ctypes.data if reqs.size else None, reqs.size,
+                                  _stream(stream)), "orng_fill_batched")
+
+
+def orng_fill_each(reqs, stream=None):
+    assert reqs.dtype.itemsize == 48 and reqs.flags["C_CONTIGUOUS"]
+    _check(_lib.orng_fill_each(reqs.ctypes.data if reqs.size else None, reqs.size,
+                               _stream(stream)), "orng_fill_each")
+
+
+def orng_autotune(gen, dist, cache_path=None):
+    _check(_lib.orng_autotune(gen, dist, cache_path.encode() if cache_path else None),
+           "orng_autotune")
+
+
+def orng_tune_load(cache_path):
+    _check(_lib.orng_tune_load(cache_path.encode()), "orng_tune_load")
 
 
 # -------- convenience wrappers that allocate the output tensor ---------------

@@ -1,0 +1,168 @@
+"""GPU parity of the batched path: every request of a batch equals the oracle's
+fill of the same (gen, dist, seed, ctr, offset, n), bit for bit, whatever the
+batch around it, the launch shape or the number of graph replays."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_19925_amd import orng
+    orng.orng_reset_launch()
+    return orng
+
+
+def _random_batch(rng, m, max_log2=14, gens=range(5), dists=range(3)):
+    L = np.maximum(1, np.floor(2.0 ** (max_log2 * rng.random(m)))).astype(np.int64)
+    gen = rng.choice(list(gens), m)
+    dist = rng.choice(list(dists), m)
+    seed = rng.integers(0, 2**63, m, dtype=np.int64).astype(np.uint64) * 2 + 1
+    ctr = rng.integers(0, 2**32, m, dtype=np.uint64)
+    off = np.floor(rng.random(m) * (2**32 - L + 1)).astype(np.uint64)
+    off[: m // 10] = rng.integers(0, 64, m // 10)           # near the stream start
+    off[m // 10: m // 5] = 2**32 - L[m // 10: m // 5]       # ending at the period
+    return gen, dist, seed, ctr, off, L
+
+
+def _run_and_check(R, O, gen, dist, seed, ctr, off, L, pad=3, each=False):
+    m = len(L)
+    starts = np.zeros(m + 1, np.int64)
+    np.cumsum(L + 1, out=starts[1:])  # one guard word between requests
+    buf = torch.full((int(starts[-1]) + pad + 1,), -1, dtype=torch.int32, device="cuda")
+    base = buf.data_ptr() + 4 * pad
+    reqs = R.make_requests(gen, dist, seed, ctr, off, L, base + 4 * starts[:-1])
+    (R.orng_fill_each if each else R.orng_fill_batched)(reqs)
+    torch.cuda.synchronize()
+    host = buf.cpu().numpy().view(np.uint32)[pad:]
+    for i in range(m):
+        got = host[starts[i]:starts[i] + L[i]]
+        ref = O.fill(int(gen[i]), int(dist[i]), int(seed[i]), int(ctr[i]), int(off[i]), int(L[i]))
+        assert np.array_equal(got, ref.view(np.uint32)), ("request", i, int(gen[i]), int(dist[i]))
+        assert host[starts[i] + L[i]] == 0xFFFFFFFF, ("guard overwritten after request", i)
+    return host
+
+
+def test_batched_mixed_parity(R, O):
+    rng = np.random.default_rng(1)
+    _run_and_check(R, O, *_random_batch(rng, 400))
+
+
+def test_each_matches_oracle(R, O):
+    rng = np.random.default_rng(2)
+    _run_and_check(R, O, *_random_batch(rng, 100), each=True)
+
+
+def test_batched_graph_replays_with_eager_work_between(R, O):
+    """Same-size batches replay one captured graph; a bigger one recaptures."""
+    rng = np.random.default_rng(3)
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for rep in range(6):
+        m = 200 if rep < 4 else 3000
+        print("replay", rep, "requests", m, flush=True)
+        _run_and_check(R, O, *_random_batch(rng, m, max_log2=12 if m > 1000 else 14))
+        scratch.add_(1.0)  # eager work on the same stream between replays
+        torch.cuda.synchronize()
+        assert float(scratch[0]) == rep + 1
+
+
+def test_batched_launch_shape_invariance(R, O):
+    rng = np.random.default_rng(4)
+    batch = _random_batch(rng, 150)
+    try:
+        for wg, mx in [(64, 1), (512, 3), (256, 0), (128, 1000)]:
+            R.orng_set_launch(wg_size=wg, max_wgs=mx)
+            _run_and_check(R, O, *batch)
+    finally:
+        R.orng_reset_launch()
+
+
+def test_batched_tyche_and_single_word_requests(R, O):
+    m = 500
+    L = np.ones(m, np.int64)
+    L[::7] = 16384 + 3
+    gen = np.full(m, 4)
+    dist = np.arange(m) % 3
+    seed = np.arange(m, dtype=np.uint64) * 977 + 5
+    ctr = np.arange(m, dtype=np.uint64)
+    off = (np.arange(m, dtype=np.uint64) * 4099) % (2**32 - 20000)
+    _run_and_check(R, O, gen, dist, seed, ctr, off, L)
+
+
+def test_batched_errors(R):
+    buf = torch.empty(64, dtype=torch.int32, device="cuda")
+    good = R.make_requests(0, 0, 1, 1, 0, 16, buf.data_ptr())
+    bad = R.make_requests([0, 7], 0, 1, 1, 0, 16, buf.data_ptr())
+    R.orng_fill_batched(good)
+    with pytest.raises(R.OrngError) as e:
+        R.orng_fill_batched(bad)
+    assert e.value.status == R.EINVAL
+    rng_bad = R.make_requests(0, 0, 1, 1, 2**32 - 8, 16, buf.data_ptr())
+    with pytest.raises(R.OrngError) as e:
+        R.orng_fill_batched(rng_bad)
+    assert e.value.status == R.ERANGE
+    odd = R.make_requests(0, 0, 1, 1, 0, 16, buf.data_ptr() + 2)
+    with pytest.raises(R.OrngError) as e:
+        R.orng_fill_batched(odd)
+    assert e.value.status == R.EINVAL
+    empty = R.make_requests(0, 0, 1, 1, 0, 0, 0)
+    R.orng_fill_batched(empty)
+
+
+def test_batched_uneven_config_sampled(R, O):
+    """10^5 Philox u32 streams, lengths log-uniform in [1, 2^20], random seeds,
+    counters and offsets, outputs packed back to back: sampled positions of
+    sampled requests against the oracle, and batched == one launch per stream."""
+    from paper_2310_19925_amd import inputs
+    b = inputs.batched_requests()
+    m = b["n"].size
+    total = int(b["out_off"][-1])
+    buf = torch.empty(total, dtype=torch.int32, device="cuda")
+    reqs = R.make_requests(0, 0, b["seed"], b["ctr"], b["offset"], b["n"],
+                           buf.data_ptr() + 4 * b["out_off"][:-1])
+    R.orng_fill_batched(reqs)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    pick = rng.choice(m, 400, replace=False)
+    idx, pos, who = [], [], []
+    for i in pick:
+        L = int(b["n"][i])
+        js = np.unique(np.concatenate([[0, L - 1], rng.integers(0, L, 6)]))
+        idx.extend(int(b["out_off"][i]) + js)
+        pos.extend(int(b["offset"][i]) + js)
+        who.extend([i] * js.size)
+    got = buf[torch.tensor(idx, device="cuda")].cpu().numpy().view(np.uint32)
+    who, pos = np.array(who), np.array(pos, np.uint64)
+    for i in pick:
+        sel = who == i
+        ref = O.samples_at(0, 0, int(b["seed"][i]), np.full(sel.sum(), b["ctr"][i], np.uint32),
+                           pos[sel])
+        assert np.array_equal(got[sel], ref), ("request", i)
+    # plain path: same request list, one launch each, then compare samples
+    snap = buf[torch.tensor(idx, device="cuda")].clone()
+    buf.fill_(-1)
+    R.orng_fill_each(reqs)
+    torch.cuda.synchronize()
+    assert torch.equal(buf[torch.tensor(idx, device="cuda")], snap)
+    del buf
+    torch.cuda.empty_cache()
+
+
+def test_autotune_writes_cache_and_keeps_results(R, O, tmp_path):
+    path = str(tmp_path / "tune.txt")
+    R.orng_autotune(0, 1, path)
+    text = open(path).read()
+    assert text.startswith("#") and len(text.strip().split("\n")) == 16
+    R.orng_tune_load(path)
+    rng = np.random.default_rng(6)
+    _run_and_check(R, O, *_random_batch(rng, 100, gens=[0], dists=[1]))
+    out = R.fill(0, 1, 9, 9, 3, 100003)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), O.fill(0, 1, 9, 9, 3, 100003).view(np.uint32))
