@@ -33,7 +33,7 @@ struct DevReq {             // 64 bytes, read by the kernel with scalar loads
     uint64_t tile_start;    // number of the request's first tile in the batch
     uint32_t ctr;
     uint32_t unroll;        // blocks per lane per tile (counter generators)
-    uint32_t flags;         // gen | dist << 4 | aligned << 8
+    uint32_t flags;         // gen | dist << 4 | delta << 8
     uint32_t pad;
 };
 static_assert(sizeof(DevReq) == 64, "DevReq layout");
@@ -69,7 +69,7 @@ __device__ __forceinline__ void run_tile(const DevReq *reqs, const uint32_t *map
     const KeySched ks = make_keysched(q.seed);
     const int gen = (int)(q.flags & 15u), dist = (int)((q.flags >> 4) & 15u);
     process_span_any<NT>(gen, dist, ks, q.ctr, q.out, q.p0, q.p0 + q.n, span, q.unroll,
-                         (q.flags >> 8) & 1u, lane);
+                         (q.flags >> 8) & 3u, lane);
 }
 
 template <bool NT>
@@ -258,8 +258,8 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
         d.ctr = r.ctr;
         d.unroll = unr[k];
         const uint64_t addr_words = reinterpret_cast<uintptr_t>(r.out) / 4;
-        const uint32_t aligned = ((addr_words - r.offset) & 3u) == 0;
-        d.flags = r.gen | (r.dist << 4) | (aligned << 8);
+        const uint32_t delta = (uint32_t)((addr_words - r.offset) & 3u);
+        d.flags = r.gen | (r.dist << 4) | (delta << 8);
         d.pad = 0;
         for (uint64_t t = 0; t < cnt[k]; ++t) map[ts + t] = (uint32_t)k;
         ts += cnt[k];

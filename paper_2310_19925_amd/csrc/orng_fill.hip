@@ -14,8 +14,8 @@
 // k*64 + l, k = 0..63, which is the same store pattern.  Spans are numbered
 // in absolute block space, so a fill that starts mid-span simply masks the
 // blocks in front of its first position.  Blocks that straddle the start or
-// end of the range, and any output whose address is not 16-byte aligned with
-// respect to the block grid, are written one dword at a time.
+// end of the range are written one dword at a time; an output whose address
+// is not 16-byte aligned with the block grid is realigned across lanes.
 #include "orng_internal.hpp"
 #include "orng_span.hpp"
 
@@ -31,7 +31,7 @@ struct SpanArgs {
     uint64_t total_spans;      // n_streams * spans_per_stream
     uint32_t ctr0;             // counter of stream 0
     uint32_t unroll;           // U (counter generators)
-    uint32_t aligned;          // 16-byte stores are legal
+    uint32_t delta;            // (stream 0 output address in words - p0) mod 4
 };
 
 template <int G, int D, bool NT>
@@ -50,7 +50,8 @@ __global__ __launch_bounds__(512) void k_span(SpanArgs a) {
         const uint64_t span = a.first_span + sl;
         const uint32_t ctr = a.ctr0 + (uint32_t)si;
         char *base = a.out + si * a.n * 4;
-        process_span<G, D, NT>(a.ks, ctr, base, a.p0, pend, span, a.unroll, a.aligned, lane);
+        const uint32_t delta = (a.delta + (uint32_t)(si * a.n)) & 3u;
+        process_span<G, D, NT>(a.ks, ctr, base, a.p0, pend, span, a.unroll, delta, lane);
     }
 }
 
@@ -129,6 +130,7 @@ hipError_t launch_fill(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t
     const bool nt = cfg.nontemporal ? cfg.nontemporal == 1 : tuned_fill(gen, dist).nontemporal == 1;
     const uint64_t addr_words = reinterpret_cast<uintptr_t>(out) / 4;
     const bool aligned = ((addr_words - offset) & 3u) == 0 && (n_streams == 1 || per_stream % 4 == 0);
+    const uint32_t delta = (uint32_t)((addr_words - offset) & 3u);
     const uint64_t first_block = offset / 4;
     const uint64_t last_block = (offset + per_stream - 1) / 4;
     const uint64_t bps = last_block - first_block + 1;
@@ -157,7 +159,7 @@ hipError_t launch_fill(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t
     a.p0 = offset;
     a.n = per_stream;
     a.ctr0 = ctr0;
-    a.aligned = aligned;
+    a.delta = delta;
     const Tuned tu = tuned_fill(gen, dist);
     a.unroll = gen == G_TYCHE ? 64 : (cfg.unroll ? cfg.unroll : tu.unroll);
     const uint64_t sb = span_blocks(gen, a.unroll);

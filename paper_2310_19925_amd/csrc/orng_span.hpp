@@ -7,7 +7,7 @@
 // substream through blocks k*64 + l, k = 0..63 (the Tyche stream layout).
 // Spans are numbered in absolute block space of the stream; blocks outside
 // [p0, pend) are masked.  Blocks straddling the range ends, and outputs whose
-// address is not 16-byte aligned with the block grid, are stored per dword.
+// address is not 16-byte aligned with the block grid, go through SpanOut.
 #pragma once
 
 #include "orng_device.hpp"
@@ -45,10 +45,81 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
 
+// Output writer of one span.  delta = (output address in words - p0) mod 4.
+// delta == 0: block b maps onto one 16-byte chunk.  delta != 0: the chunk
+// that holds the head of block b also holds the last delta words of block
+// b - 1; lane l takes them from lane l - 1 (cross-lane shift) and lane 0 from
+// lane 63 of the previous iteration (carried in uniform registers), so every
+// interior chunk is still one 16-byte store.  Lane 63 writes its block's tail
+// itself when no further iteration of the span follows; lane 0 of the first
+// iteration writes only its own words.  Positions outside [p0, pend) are never
+// written.
+struct SpanOut {
+    char *base;
+    uint64_t p0, pend;
+    uint32_t delta;
+    bool have_carry;
+    uint32_t carry[4];
+};
+
+template <bool NT>
+__device__ __forceinline__ void put_word(const SpanOut &o, int64_t q, uint32_t v) {
+    if (q >= (int64_t)o.p0 && q < (int64_t)o.pend)
+        reinterpret_cast<uint32_t *>(o.base)[q - (int64_t)o.p0] = v;
+}
+
+template <bool NT>
+__device__ __forceinline__ void emit_block(SpanOut &o, uint64_t b, const uint32_t w[4],
+                                           uint32_t lane, bool last_iter) {
+    if (o.delta == 0) {
+        store_block<NT>(o.base, b * 4, o.p0, o.pend, true, w);
+        return;
+    }
+    const int d = (int)o.delta;
+    uint32_t prev[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        prev[j] = __shfl_up(w[j], 1, 64);
+        if (lane == 0) prev[j] = o.carry[j];
+    }
+    const bool prev_ok = lane > 0 || o.have_carry;
+    const int64_t q0 = (int64_t)(b * 4) - d;  // first position of the chunk
+    uint32_t v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        // chunk word j: position q0 + j; from the previous block if j < d
+        const uint32_t from_prev = d == 1 ? prev[3] : d == 2 ? prev[2 + (j & 1)] : prev[(1 + j) & 3];
+        const uint32_t from_own = d == 1 ? w[(j + 3) & 3] : d == 2 ? w[(j + 2) & 3] : w[(j + 1) & 3];
+        v[j] = j < d ? from_prev : from_own;
+    }
+    if (prev_ok && q0 >= (int64_t)o.p0 && q0 + 4 <= (int64_t)o.pend) {
+        store16<NT>(o.base + 4 * (q0 - (int64_t)o.p0), v);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j >= d || prev_ok) put_word<NT>(o, q0 + j, v[j]);
+    }
+    if (last_iter && lane == 63) {
+        // tail of this block: words 4 - d .. 3 at positions 4b + 4 - d .. 4b + 3
+#pragma unroll
+        for (int j = 1; j <= 3; ++j)
+            if (j <= d) put_word<NT>(o, (int64_t)(b * 4) + 4 - j, w[4 - j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o.carry[j] = __builtin_amdgcn_readlane(w[j], 63);
+    o.have_carry = true;
+}
+
 template <int G, int D, bool NT>
 __device__ __forceinline__ void process_span(const KeySched &ks, uint32_t ctr, char *base,
                                              uint64_t p0, uint64_t pend, uint64_t span,
-                                             uint32_t unroll, bool aligned, uint32_t lane) {
+                                             uint32_t unroll, uint32_t delta, uint32_t lane) {
+    SpanOut o;
+    o.base = base;
+    o.p0 = p0;
+    o.pend = pend;
+    o.delta = delta;
+    o.have_carry = false;
     if constexpr (G == G_TYCHE) {
         Tyche st;
         st.seed(ks, (uint32_t)span * 64u + lane, ctr);
@@ -58,22 +129,29 @@ __device__ __forceinline__ void process_span(const KeySched &ks, uint32_t ctr, c
             if (bw * 4 >= pend) break;
             uint32_t w[4];
             st.next4(w);
-            const uint64_t p = (bw + lane) * 4;
-            if (p + 4 <= p0) continue;
+            if ((bw + 64) * 4 <= p0) {  // whole iteration before p0
+                o.have_carry = false;
+                continue;
+            }
             convert4<D>(w);
-            store_block<NT>(base, p, p0, pend, aligned, w);
+            const bool last = k == 63 || (bw + 64) * 4 >= pend;
+            emit_block<NT>(o, bw + lane, w, lane, last);
         }
     } else {
         const uint64_t b0 = span * 64u * unroll;
         for (uint32_t u = 0; u < unroll; ++u) {
             const uint64_t bw = b0 + 64u * u;
             if (bw * 4 >= pend) break;
-            if ((bw + 64) * 4 <= p0) continue;
+            if ((bw + 64) * 4 <= p0) {
+                o.have_carry = false;
+                continue;
+            }
             const uint64_t b = bw + lane;
             uint32_t w[4];
             counter_block<G>((uint32_t)b, ctr, ks, w);
             convert4<D>(w);
-            store_block<NT>(base, b * 4, p0, pend, aligned, w);
+            const bool last = u + 1 == unroll || (bw + 64) * 4 >= pend;
+            emit_block<NT>(o, b, w, lane, last);
         }
     }
 }
@@ -83,10 +161,10 @@ template <bool NT>
 __device__ __forceinline__ void process_span_any(int gen, int dist, const KeySched &ks,
                                                  uint32_t ctr, char *base, uint64_t p0,
                                                  uint64_t pend, uint64_t span, uint32_t unroll,
-                                                 bool aligned, uint32_t lane) {
+                                                 uint32_t delta, uint32_t lane) {
 #define ORNG_CASE(G, D)                                                                    \
     case G * 3 + D:                                                                        \
-        process_span<G, D, NT>(ks, ctr, base, p0, pend, span, unroll, aligned, lane);      \
+        process_span<G, D, NT>(ks, ctr, base, p0, pend, span, unroll, delta, lane);        \
         break;
     switch (gen * 3 + dist) {
         ORNG_CASE(0, 0) ORNG_CASE(0, 1) ORNG_CASE(0, 2)
