@@ -111,6 +111,84 @@ def bench_batched(orng, inputs, stream, dev):
             "batched_vs_each": round(t_each / t_batched, 2)}
 
 
+def _replay(orng, tr, idx, arena_bytes, open_loop):
+    """Submit the requests of trace `tr` selected by `idx` to a fresh server
+    (server-allocated outputs), at their arrival times (open loop) or all at
+    once (saturated); a second thread waits for each ticket in order and
+    releases it right after completion.  Returns the server statistics."""
+    import threading
+    srv = orng.orng_serve_create(arena_bytes)
+    tickets = [None] * len(idx)
+    ready = threading.Semaphore(0)
+
+    def releaser():
+        for k in range(len(idx)):
+            ready.acquire()
+            orng.orng_serve_wait(srv, tickets[k])
+            orng.orng_serve_release(srv, tickets[k])
+
+    th = threading.Thread(target=releaser)
+    th.start()
+    t0 = time.perf_counter()
+    for k, i in enumerate(idx):
+        if open_loop:
+            dt = t0 + float(tr["t"][i]) - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+        tickets[k] = orng.orng_serve_submit(srv, int(tr["gen"][i]), int(tr["dist"][i]),
+                                            int(tr["seed"][i]), int(tr["ctr"][i]),
+                                            int(tr["offset"][i]), int(tr["n"][i]))
+        ready.release()
+    th.join()
+    st = orng.orng_serve_stats(srv)
+    orng.orng_serve_destroy(srv)
+    return st
+
+
+def bench_serve(orng, inputs, stream, dev):
+    """Poisson arrivals (mean 5,000/s) of mixed fill requests, sizes
+    log-uniform in [2^10, 2^26] words, four generator families x three
+    distributions, 32 GB arena: open-loop replay (latency) and saturated
+    replay of the same trace (throughput) vs one plain launch per request."""
+    import numpy as np
+    import torch
+    tr = inputs.serve_trace()
+    m = tr["n"].size
+    idx = np.arange(m)
+    words = int(tr["n"].sum())
+    op = _replay(orng, tr, idx, 32 << 30, True)
+    sat = _replay(orng, tr, idx, 32 << 30, False)
+    # plain path on the same requests: one fill launch each, outputs in a ring
+    cap = 8 << 30  # words
+    buf = torch.empty(cap, dtype=torch.int32, device=dev)
+    offs, pos = np.zeros(m, np.int64), 0
+    for i in range(m):
+        if pos + int(tr["n"][i]) > cap:
+            pos = 0
+        offs[i] = pos
+        pos += (int(tr["n"][i]) + 63) // 64 * 64
+    reqs = orng.make_requests(tr["gen"], tr["dist"], tr["seed"], tr["ctr"], tr["offset"],
+                              tr["n"], buf.data_ptr() + 4 * offs)
+    t_plain = _time_events(stream, lambda: orng.orng_fill_each(reqs, stream), 2)
+    del buf
+    torch.cuda.empty_cache()
+    gs = lambda st: round(st["samples_done"] / st["first_submit_to_last_done_s"] / 1e9, 2)
+    plain = words / (t_plain * 1e-3) / 1e9
+    return {"requests": int(m), "samples": words, "offered_req_per_s": 5000,
+            "open_loop": {"p50_ms": round(op["latency_p50_ms"], 4),
+                          "p99_ms": round(op["latency_p99_ms"], 4),
+                          "mean_ms": round(op["latency_mean_ms"], 4),
+                          "gsamples_s": gs(op), "steps": op["steps"],
+                          "active_peak": op["active_peak"],
+                          "arena_peak_gb": round(op["arena_peak_bytes"] / 1e9, 3)},
+            "saturated": {"gsamples_s": gs(sat), "p50_ms": round(sat["latency_p50_ms"], 3),
+                          "p99_ms": round(sat["latency_p99_ms"], 3), "steps": sat["steps"],
+                          "active_peak": sat["active_peak"],
+                          "arena_peak_gb": round(sat["arena_peak_bytes"] / 1e9, 3)},
+            "plain_each_gsamples_s": round(plain, 2),
+            "saturated_vs_plain": round(gs(sat) / plain, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +197,7 @@ def main():
     ap.add_argument("--no-walk", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--only", default="", help="gen:dist list to restrict the fills (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -222,6 +301,9 @@ def main():
 
     if not args.no_batched:
         result["batched"] = bench_batched(orng, inputs, stream, dev)
+
+    if not args.no_serve:
+        result["served"] = bench_serve(orng, inputs, stream, dev)
 
     if not args.no_cpu:
         log("cpu baseline ...")

@@ -166,6 +166,69 @@ int orng_fill_each(const orng_req_t *h_reqs, size_t nreq, void *stream);
 int orng_autotune(int gen, int dist, const char *cache_path);
 int orng_tune_load(const char *cache_path);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of fill requests (the request loop built on the
+ * stream model of section 3.1).  A server owns one HIP stream on the device
+ * that is current at orng_serve_create, an HBM arena for outputs it
+ * allocates, and a table of device-resident slots holding the stream state of
+ * every admitted request (seed, counter, position range, output).  Requests
+ * are admitted in arrival order as slots and arena space free up; each device
+ * step generates tiles of all admitted requests in one launch, and up to two
+ * steps are in flight, so requests that arrive while others run join the next
+ * step and their work overlaps on the device.  Results are bit-identical to
+ * orng_fill of the same request, alone or in any mix.
+ * ------------------------------------------------------------------------- */
+typedef struct orng_server orng_server_t;
+
+typedef struct {
+    void *arena;            /* device memory for server-allocated outputs; NULL: the
+                               server allocates arena_bytes itself */
+    uint64_t arena_bytes;   /* HBM budget for outputs in flight (> 0) */
+    uint32_t max_slots;     /* requests resident on the device at once (0: 4096) */
+    uint32_t flags;         /* reserved, 0 */
+    uint64_t step_words;    /* most words generated per device step (0: automatic) */
+} orng_serve_cfg_t;
+
+typedef struct {
+    void *d_out;            /* device address of the result (arena or caller buffer) */
+    uint64_t n;             /* samples */
+    int64_t t_submit_ns;    /* CLOCK_MONOTONIC time of orng_serve_submit */
+    int64_t t_admit_ns;     /* time the request got a slot (and arena space) */
+    int64_t t_done_ns;      /* time the server observed its last tile complete */
+    int32_t status;         /* ORNG_OK, or the error that ended the request */
+    int32_t pad;
+} orng_result_t;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, released, failed;
+    uint64_t samples_done;  /* samples of completed requests */
+    uint64_t steps;         /* device launches */
+    uint64_t arena_peak_bytes;
+    uint32_t active_peak;   /* most requests resident at once */
+    uint32_t queued;        /* waiting for admission now */
+    double latency_p50_ms, latency_p99_ms, latency_mean_ms; /* submit -> done, completed */
+    double first_submit_to_last_done_s;
+} orng_serve_stats_t;
+
+/* Create a server.  Errors: EINVAL (cfg), EHIP (stream/arena allocation). */
+int orng_serve_create(const orng_serve_cfg_t *cfg, orng_server_t **srv);
+/* Queue a request; never blocks on the device.  req->out == NULL asks the
+   server for an arena output (released by orng_serve_release); otherwise the
+   caller's buffer is written.  Errors: EINVAL/ERANGE (as orng_fill), ENOMEM
+   (output larger than the arena), EBUSY (server shutting down). */
+int orng_serve_submit(orng_server_t *srv, const orng_req_t *req, uint64_t *ticket);
+/* ORNG_OK and *res when done, ORNG_EBUSY while queued or running, ENOENT for
+   unknown or released tickets. */
+int orng_serve_poll(orng_server_t *srv, uint64_t ticket, orng_result_t *res);
+/* As poll, waiting up to timeout_ns (< 0: forever). */
+int orng_serve_wait(orng_server_t *srv, uint64_t ticket, int64_t timeout_ns, orng_result_t *res);
+/* Forget a finished ticket and return its arena range.  EBUSY if not finished. */
+int orng_serve_release(orng_server_t *srv, uint64_t ticket);
+/* Counters and latency percentiles (nearest rank over completed requests). */
+int orng_serve_stats(orng_server_t *srv, orng_serve_stats_t *st);
+/* Drain queued and in-flight work, then free the server (caller memory untouched). */
+int orng_serve_destroy(orng_server_t *srv);
+
 /* Launch knobs for the fill kernels (0 = automatic).  They change speed
    only, never results.  Process-wide; NULL restores the defaults. */
 typedef struct {

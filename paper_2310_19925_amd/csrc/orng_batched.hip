@@ -11,7 +11,9 @@
 // two copies into a device buffer whose layout is fixed for its capacity.
 // Device: a persistent grid pulls tiles from an atomic cursor in the header
 // (`chunk` tiles per pull), looks up the request of each tile in the map and
-// generates it with the same span code as the plain fill.  The launch is
+// generates it with the same span code as the plain fill.  A static schedule
+// (one wave per tile, no queue) is the alternative the tuner may pick: short
+// waves keep more stores in flight than long-lived ones on this part.  The launch is
 // captured once into a hipGraph per (buffer, launch shape) and replayed.
 // A small ring of such contexts per device lets consecutive calls overlap:
 // a context is reused only after the event of its previous launch.
@@ -89,6 +91,17 @@ __global__ __launch_bounds__(512) void k_batched(BatchView v) {
     }
 }
 
+// Static schedule: wave w of the grid generates tile w (the grid is rounded up
+// to a size bucket so that a captured graph serves many batch sizes; waves
+// past the last tile exit at once).
+template <bool NT>
+__global__ __launch_bounds__(512) void k_batched_static(BatchView v) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t t = wave_uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    if (t >= v.hdr->total_tiles) return;
+    run_tile<NT>(v.reqs, v.map, t, lane);
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -151,7 +164,16 @@ static hipError_t ensure_capacity(BatchCtx &c, uint64_t nreq, uint64_t tiles) {
 struct BatchShape {
     uint32_t wg, grid, chunk;
     bool nt;
+    bool persistent;
 };
+
+// Smallest bucket >= x with 1/8 granularity (keeps captured graphs reusable).
+static uint64_t bucket(uint64_t x) {
+    if (x <= 64) return x;
+    int k = 63 - __builtin_clzll(x);
+    const uint64_t step = 1ull << (k - 3);
+    return (x + step - 1) / step * step;
+}
 
 static BatchShape batch_shape(int gen, int dist, uint64_t tiles) {
     const Tuned tu = tuned_fill(gen, dist);
@@ -159,17 +181,27 @@ static BatchShape batch_shape(int gen, int dist, uint64_t tiles) {
     BatchShape s;
     s.wg = cfg.wg_size ? cfg.wg_size : tu.b_wg_size;
     s.chunk = tu.b_chunk ? tu.b_chunk : 1;
-    uint64_t grid = (uint64_t)device_cu_count() * (tu.b_wgs_per_cu ? tu.b_wgs_per_cu : 8);
-    if (cfg.max_wgs) grid = cfg.max_wgs;
-    const uint64_t need = (tiles + (s.wg / 64) - 1) / (s.wg / 64);
-    s.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(grid, need));
     s.nt = false;
+    const uint64_t wpg = s.wg / 64;
+    // b_wgs_per_cu == 0 selects the static one-wave-per-tile schedule
+    s.persistent = tu.b_wgs_per_cu != 0 || cfg.max_wgs != 0;
+    if (s.persistent) {
+        uint64_t grid = (uint64_t)device_cu_count() * (tu.b_wgs_per_cu ? tu.b_wgs_per_cu : 4);
+        if (cfg.max_wgs) grid = cfg.max_wgs;
+        const uint64_t need = (tiles + wpg - 1) / wpg;
+        s.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(grid, need));
+    } else {
+        s.grid = (uint32_t)((bucket(tiles) + wpg - 1) / wpg);
+    }
     return s;
 }
 
-static void *batched_kernel(bool nt) {
-    return nt ? reinterpret_cast<void *>(&k_batched<true>)
-              : reinterpret_cast<void *>(&k_batched<false>);
+static void *batched_kernel(const BatchShape &s) {
+    if (s.persistent)
+        return s.nt ? reinterpret_cast<void *>(&k_batched<true>)
+                    : reinterpret_cast<void *>(&k_batched<false>);
+    return s.nt ? reinterpret_cast<void *>(&k_batched_static<true>)
+                : reinterpret_cast<void *>(&k_batched_static<false>);
 }
 
 int validate_request(const orng_req_t &r) {
@@ -276,12 +308,12 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     void *args[] = {&v};
     if (use_graphs()) {
         const uint64_t key[4] = {reinterpret_cast<uintptr_t>(c.d_buf), sh.wg, sh.grid,
-                                 (uint64_t)sh.nt};
+                                 (uint64_t)sh.nt | ((uint64_t)sh.persistent << 1)};
         if (!c.exec || std::memcmp(key, c.graph_key, sizeof key) != 0) {
             if (c.exec) { hipGraphExecDestroy(c.exec); c.exec = nullptr; }
             if (c.graph) { hipGraphDestroy(c.graph); c.graph = nullptr; }
             ORNG_TRY(hipStreamBeginCapture(db->capture, hipStreamCaptureModeThreadLocal));
-            hipError_t le = hipLaunchKernel(batched_kernel(sh.nt), dim3(sh.grid), dim3(sh.wg),
+            hipError_t le = hipLaunchKernel(batched_kernel(sh), dim3(sh.grid), dim3(sh.wg),
                                             args, 0, db->capture);
             hipError_t ce = hipStreamEndCapture(db->capture, &c.graph);
             ORNG_TRY(le);
@@ -291,7 +323,7 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
         }
         ORNG_TRY(hipGraphLaunch(c.exec, stream));
     } else {
-        ORNG_TRY(hipLaunchKernel(batched_kernel(sh.nt), dim3(sh.grid), dim3(sh.wg), args, 0,
+        ORNG_TRY(hipLaunchKernel(batched_kernel(sh), dim3(sh.grid), dim3(sh.wg), args, 0,
                                  stream));
     }
     ORNG_TRY(hipEventRecord(c.done, stream));

@@ -78,7 +78,7 @@ static bool sane(const Tuned &t, int gen) {
     auto wg_ok = [](uint32_t w) { return w >= 64 && w <= 512 && w % 64 == 0; };
     return wg_ok(t.wg_size) && wg_ok(t.b_wg_size) && t.unroll >= 1 && t.unroll <= 64 &&
            t.b_unroll >= 1 && t.b_unroll <= 64 && t.b_chunk >= 1 && t.b_chunk <= 64 &&
-           t.b_wgs_per_cu >= 1 && t.b_wgs_per_cu <= 64 && t.nontemporal >= 1 &&
+           t.b_wgs_per_cu <= 64 && t.nontemporal >= 1 &&
            t.nontemporal <= 2 && (gen != G_TYCHE || t.unroll == 64);
 }
 
@@ -194,7 +194,7 @@ int orng_autotune(int gen, int dist, const char *cache_path) {
                     t.max_wgs = cap;
                     t.nontemporal = nt;
                     set_tuned(gen, dist, t);
-                    const float ms = time_ms(s, 3, [&] {
+                    const float ms = time_ms(s, 5, [&] {
                         launch_fill(gen, dist, 0x5EED, 0, 1, 0, n, buf, s);
                     }, &e);
                     if (ms < best_ms) { best_ms = ms; best.wg_size = wg; best.unroll = t.unroll;
@@ -206,7 +206,7 @@ int orng_autotune(int gen, int dist, const char *cache_path) {
     std::mt19937_64 rng(12345);
     std::vector<orng_req_t> reqs;
     uint64_t used = 0;
-    while (reqs.size() < 2048) {
+    while (reqs.size() < 8192) {
         const double u = std::uniform_real_distribution<double>(0.0, 20.0)(rng);
         uint64_t len = (uint64_t)std::pow(2.0, u);
         if (len < 1) len = 1;
@@ -225,12 +225,13 @@ int orng_autotune(int gen, int dist, const char *cache_path) {
     }
     float best_b = 1e30f;
     Tuned bt = best;
-    for (uint32_t wg : {256u, 512u})
-        for (uint32_t un : {4u, 8u, 16u, 32u})
-            for (uint32_t ch : {1u, 2u, 4u})
-                for (uint32_t wpc : {4u, 8u, 16u}) {
+    for (uint32_t wg : {128u, 256u, 512u})
+        for (uint32_t un : {2u, 4u, 8u, 16u, 32u, 64u})
+            for (uint32_t ch : {1u, 2u, 4u, 8u})
+                for (uint32_t wpc : {0u, 1u, 2u, 4u, 8u}) {  // 0: static schedule
                     if (e != hipSuccess) break;
                     if (gen == G_TYCHE && un != 16) continue;
+                    if (wpc == 0 && ch != 1) continue;  // chunk is a queue parameter
                     Tuned t = best;
                     t.b_wg_size = wg;
                     t.b_unroll = un;
@@ -238,7 +239,7 @@ int orng_autotune(int gen, int dist, const char *cache_path) {
                     t.b_wgs_per_cu = wpc;
                     set_tuned(gen, dist, t);
                     int st = ORNG_OK;
-                    const float ms = time_ms(s, 3, [&] {
+                    const float ms = time_ms(s, 5, [&] {
                         st = fill_batched(reqs.data(), reqs.size(), s);
                     }, &e);
                     if (st != ORNG_OK) continue;

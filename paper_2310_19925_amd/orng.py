@@ -34,6 +34,32 @@ class orng_launch_t(C.Structure):
                 ("nontemporal", C.c_uint32)]
 
 
+class orng_serve_cfg_t(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("max_slots", C.c_uint32),
+                ("flags", C.c_uint32), ("step_words", C.c_uint64)]
+
+
+class orng_result_t(C.Structure):
+    _fields_ = [("d_out", C.c_void_p), ("n", C.c_uint64), ("t_submit_ns", C.c_int64),
+                ("t_admit_ns", C.c_int64), ("t_done_ns", C.c_int64), ("status", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class orng_serve_stats_t(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
+                ("released", C.c_uint64), ("failed", C.c_uint64), ("samples_done", C.c_uint64),
+                ("steps", C.c_uint64), ("arena_peak_bytes", C.c_uint64),
+                ("active_peak", C.c_uint32), ("queued", C.c_uint32),
+                ("latency_p50_ms", C.c_double), ("latency_p99_ms", C.c_double),
+                ("latency_mean_ms", C.c_double), ("first_submit_to_last_done_s", C.c_double)]
+
+
+class orng_req_t(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("offset", C.c_uint64), ("n", C.c_uint64),
+                ("out", C.c_void_p), ("ctr", C.c_uint32), ("gen", C.c_uint32),
+                ("dist", C.c_uint32), ("flags", C.c_uint32)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("liborng.so is not built (%s); run paper_2310_19925_amd/build.py"
@@ -48,6 +74,13 @@ def _load():
         "orng_fill_each": [vp, C.c_size_t, vp],
         "orng_autotune": [i32, i32, C.c_char_p],
         "orng_tune_load": [C.c_char_p],
+        "orng_serve_create": [C.POINTER(orng_serve_cfg_t), C.POINTER(C.c_void_p)],
+        "orng_serve_submit": [vp, C.POINTER(orng_req_t), C.POINTER(C.c_uint64)],
+        "orng_serve_poll": [vp, u64, C.POINTER(orng_result_t)],
+        "orng_serve_wait": [vp, u64, C.c_int64, C.POINTER(orng_result_t)],
+        "orng_serve_release": [vp, u64],
+        "orng_serve_stats": [vp, C.POINTER(orng_serve_stats_t)],
+        "orng_serve_destroy": [vp],
         "orng_set_launch": [C.POINTER(orng_launch_t)],
         "orng_get_launch": [C.POINTER(orng_launch_t)],
         "orng_last_hip_error": [],
@@ -165,6 +198,58 @@ def orng_autotune(gen, dist, cache_path=None):
 
 def orng_tune_load(cache_path):
     _check(_lib.orng_tune_load(cache_path.encode()), "orng_tune_load")
+
+
+def orng_serve_create(arena_bytes, arena=None, max_slots=0, step_words=0):
+    cfg = orng_serve_cfg_t(_ptr(arena), arena_bytes, max_slots, 0, step_words)
+    h = C.c_void_p()
+    _check(_lib.orng_serve_create(C.byref(cfg), C.byref(h)), "orng_serve_create")
+    return h.value
+
+
+def orng_serve_submit(srv, gen, dist, seed, ctr, offset, n, out=None):
+    r = orng_req_t(seed, offset, n, _ptr(out), ctr, gen, dist, 0)
+    t = C.c_uint64()
+    _check(_lib.orng_serve_submit(srv, C.byref(r), C.byref(t)), "orng_serve_submit")
+    return t.value
+
+
+def _result(res):
+    return dict(d_out=res.d_out, n=res.n, t_submit_ns=res.t_submit_ns,
+                t_admit_ns=res.t_admit_ns, t_done_ns=res.t_done_ns, status=res.status)
+
+
+def orng_serve_poll(srv, ticket):
+    """Returns the result dict when done, None while queued or running."""
+    res = orng_result_t()
+    st = _lib.orng_serve_poll(srv, ticket, C.byref(res))
+    if st == EBUSY:
+        return None
+    _check(st, "orng_serve_poll")
+    return _result(res)
+
+
+def orng_serve_wait(srv, ticket, timeout_ns=-1):
+    res = orng_result_t()
+    st = _lib.orng_serve_wait(srv, ticket, timeout_ns, C.byref(res))
+    if st == EBUSY:
+        return None
+    _check(st, "orng_serve_wait")
+    return _result(res)
+
+
+def orng_serve_release(srv, ticket):
+    _check(_lib.orng_serve_release(srv, ticket), "orng_serve_release")
+
+
+def orng_serve_stats(srv):
+    st = orng_serve_stats_t()
+    _check(_lib.orng_serve_stats(srv, C.byref(st)), "orng_serve_stats")
+    return {k: getattr(st, k) for k, _ in orng_serve_stats_t._fields_}
+
+
+def orng_serve_destroy(srv):
+    _check(_lib.orng_serve_destroy(srv), "orng_serve_destroy")
 
 
 # -------- convenience wrappers that allocate the output tensor ---------------

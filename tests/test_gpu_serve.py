@@ -1,0 +1,175 @@
+"""GPU tests of the continuous-batching server: every result equals the oracle
+(and the same request served alone), admission respects the HBM budget, and
+the ticket life cycle and error codes behave as documented."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_19925_amd import orng
+    return orng
+
+
+def _arena(nbytes):
+    return torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+
+
+def _read(arena, res):
+    off = (res["d_out"] - arena.data_ptr()) // 4
+    torch.cuda.synchronize()
+    return arena[off:off + res["n"]].cpu().numpy().view(np.uint32)
+
+
+def _random_reqs(rng, m, lo=10, hi=16):
+    out = []
+    for _ in range(m):
+        n = int(2 ** (lo + (hi - lo) * rng.random()))
+        out.append(dict(gen=int(rng.integers(0, 5)), dist=int(rng.integers(0, 3)),
+                        seed=int(rng.integers(0, 2**63)), ctr=int(rng.integers(0, 2**32)),
+                        offset=int(rng.integers(0, 2**32 - n)), n=n))
+    return out
+
+
+def test_serve_mixed_parity(R, O):
+    rng = np.random.default_rng(1)
+    arena = _arena(64 << 20)
+    srv = R.orng_serve_create(arena.numel() * 4, arena=arena)
+    try:
+        reqs = _random_reqs(rng, 80)
+        tickets = [R.orng_serve_submit(srv, **q) for q in reqs]
+        for q, t in zip(reqs, tickets):
+            res = R.orng_serve_wait(srv, t)
+            assert res["status"] == 0 and res["n"] == q["n"]
+            assert res["t_submit_ns"] <= res["t_admit_ns"] <= res["t_done_ns"]
+            ref = O.fill(q["gen"], q["dist"], q["seed"], q["ctr"], q["offset"], q["n"])
+            assert np.array_equal(_read(arena, res), ref.view(np.uint32)), q
+            R.orng_serve_release(srv, t)
+        st = R.orng_serve_stats(srv)
+        assert st["completed"] == 80 and st["released"] == 80 and st["failed"] == 0
+        assert 0 < st["latency_p50_ms"] <= st["latency_p99_ms"]
+    finally:
+        R.orng_serve_destroy(srv)
+
+
+def test_serve_caller_outputs_and_small_steps(R, O):
+    """Caller buffers (misaligned), and a step size far below the request
+    sizes so every request spans many steps mixed with the others."""
+    rng = np.random.default_rng(2)
+    arena = _arena(1 << 20)
+    srv = R.orng_serve_create(arena.numel() * 4, arena=arena, step_words=8192)
+    try:
+        reqs = _random_reqs(rng, 20, 12, 15)
+        bufs, tickets = [], []
+        for q in reqs:
+            b = torch.full((q["n"] + 2,), -1, dtype=torch.int32, device="cuda")
+            bufs.append(b)
+            tickets.append(R.orng_serve_submit(srv, out=b.data_ptr() + 4, **q))
+        for q, t, b in zip(reqs, tickets, bufs):
+            res = R.orng_serve_wait(srv, t)
+            torch.cuda.synchronize()
+            host = b.cpu().numpy().view(np.uint32)
+            ref = O.fill(q["gen"], q["dist"], q["seed"], q["ctr"], q["offset"], q["n"])
+            assert np.array_equal(host[1:1 + q["n"]], ref.view(np.uint32))
+            assert host[0] == 0xFFFFFFFF and host[-1] == 0xFFFFFFFF
+            R.orng_serve_release(srv, t)
+        assert R.orng_serve_stats(srv)["steps"] > 20
+    finally:
+        R.orng_serve_destroy(srv)
+
+
+def test_serve_mix_equals_alone(R):
+    rng = np.random.default_rng(3)
+    probe = dict(gen=2, dist=2, seed=123456789, ctr=77, offset=1001, n=50_001)
+    arena = _arena(32 << 20)
+    srv = R.orng_serve_create(arena.numel() * 4, arena=arena)
+    try:
+        t = R.orng_serve_submit(srv, **probe)
+        alone = _read(arena, R.orng_serve_wait(srv, t)).copy()
+        R.orng_serve_release(srv, t)
+        others = _random_reqs(rng, 40)
+        ts = [R.orng_serve_submit(srv, **q) for q in others[:20]]
+        t = R.orng_serve_submit(srv, **probe)
+        ts += [R.orng_serve_submit(srv, **q) for q in others[20:]]
+        mixed = _read(arena, R.orng_serve_wait(srv, t))
+        assert np.array_equal(alone, mixed)
+        for x in ts:
+            R.orng_serve_wait(srv, x)
+            R.orng_serve_release(srv, x)
+        R.orng_serve_release(srv, t)
+    finally:
+        R.orng_serve_destroy(srv)
+
+
+def test_serve_admission_under_budget(R, O):
+    """A 1 MiB arena holds one 200k-word output at a time: the next request is
+    admitted only after the previous one is released."""
+    arena = _arena(1 << 20)
+    srv = R.orng_serve_create(arena.numel() * 4, arena=arena)
+    try:
+        qs = [dict(gen=0, dist=0, seed=i, ctr=i, offset=0, n=200_000) for i in range(4)]
+        ts = [R.orng_serve_submit(srv, **q) for q in qs]
+        first = R.orng_serve_wait(srv, ts[0])
+        time.sleep(0.05)
+        assert R.orng_serve_poll(srv, ts[1]) is None  # still waiting for arena space
+        st = R.orng_serve_stats(srv)
+        assert st["admitted"] == 1 and st["queued"] == 3
+        with pytest.raises(R.OrngError) as e:
+            R.orng_serve_release(srv, ts[1])
+        assert e.value.status == R.EBUSY
+        assert np.array_equal(_read(arena, first), O.fill(0, 0, 0, 0, 0, 200_000))
+        R.orng_serve_release(srv, ts[0])
+        for i in range(1, 4):
+            res = R.orng_serve_wait(srv, ts[i])
+            assert np.array_equal(_read(arena, res), O.fill(0, 0, i, i, 0, 200_000))
+            R.orng_serve_release(srv, ts[i])
+        assert R.orng_serve_stats(srv)["arena_peak_bytes"] <= 1 << 20
+    finally:
+        R.orng_serve_destroy(srv)
+
+
+def test_serve_errors(R):
+    arena = _arena(1 << 20)
+    srv = R.orng_serve_create(arena.numel() * 4, arena=arena)
+    try:
+        with pytest.raises(R.OrngError) as e:
+            R.orng_serve_submit(srv, 0, 0, 1, 1, 0, 1 << 20)  # 4 MiB > 1 MiB arena
+        assert e.value.status == R.ENOMEM
+        with pytest.raises(R.OrngError) as e:
+            R.orng_serve_submit(srv, 9, 0, 1, 1, 0, 16)
+        assert e.value.status == R.EINVAL
+        with pytest.raises(R.OrngError) as e:
+            R.orng_serve_submit(srv, 0, 0, 1, 1, 2**32 - 4, 16)
+        assert e.value.status == R.ERANGE
+        with pytest.raises(R.OrngError) as e:
+            R.orng_serve_release(srv, 12345)
+        assert e.value.status == R.ENOENT
+        t = R.orng_serve_submit(srv, 0, 0, 1, 1, 0, 16)
+        R.orng_serve_wait(srv, t)
+        R.orng_serve_release(srv, t)
+        with pytest.raises(R.OrngError) as e:
+            R.orng_serve_poll(srv, t)
+        assert e.value.status == R.ENOENT
+    finally:
+        R.orng_serve_destroy(srv)
+
+
+def test_serve_destroy_drains_in_flight(R, O):
+    out = torch.full((1 << 20,), -1, dtype=torch.int32, device="cuda")
+    srv = R.orng_serve_create(1 << 24)
+    for k in range(8):
+        R.orng_serve_submit(srv, 4, 1, k, k, 0, 1 << 17, out=out.data_ptr() + k * (1 << 19))
+    R.orng_serve_destroy(srv)  # returns only after all queued work ran
+    torch.cuda.synchronize()
+    host = out.cpu().numpy().view(np.uint32)
+    for k in range(8):
+        ref = O.fill(4, 1, k, k, 0, 1 << 17).view(np.uint32)
+        assert np.array_equal(host[k * (1 << 17):(k + 1) * (1 << 17)], ref)
