@@ -118,6 +118,18 @@ int orng_brownian(uint64_t seed, uint32_t ctr0, uint32_t n_particles, uint32_t d
                   double *d_msd, uint32_t msd_every, void *stream);
 
 /*
+ * orng_normal_pairs -- the library's Box-Muller transform applied to
+ * caller-supplied 32-bit words: (z0[i], z1[i]) is the normal pair made from
+ * (x0[i], x1[i]) exactly as F32_NORMAL samples 2m and 2m+1 are made from
+ * words 2m and 2m+1 (u1 = ((x0 >> 8) + 1) 2^-24, u2 = (x1 >> 8) 2^-24,
+ * z0 = R cos 2 pi u2, z1 = R sin 2 pi u2, R = sqrt(-2 ln u1)).
+ * All four arrays are device buffers of n elements, 4-byte aligned.
+ * Errors: EINVAL (NULL or misaligned pointer with n > 0), ERANGE (n > 2^40).
+ */
+int orng_normal_pairs(const uint32_t *d_x0, const uint32_t *d_x1, uint64_t n, float *d_z0,
+                      float *d_z1, void *stream);
+
+/*
  * Fill request: the arguments of one orng_fill, as a record.  48 bytes.
  *   out   : device buffer of n * 4 bytes (caller-owned, 4-byte aligned)
  *   flags : reserved, must be 0

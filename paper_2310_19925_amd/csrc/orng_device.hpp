@@ -250,6 +250,31 @@ __device__ __forceinline__ float to_uniform(uint32_t x) {
     return __uint2float_rn(x >> 8) * 0x1p-24f;
 }
 
+// n / d rounded to nearest for the operands ln_u1 produces (d = m + 1 in
+// [1.70, 2.42], n = m - 1 in [-0.30, 0.42]): hardware reciprocal estimate,
+// one Newton step, then one residual correction of the quotient (Markstein).
+// The GPU test-suite checks it against the IEEE quotient for every one of
+// the 2^24 arguments of ln_u1.
+__device__ __forceinline__ float div_ln(float n, float d) {
+    float r = __builtin_amdgcn_rcpf(d);
+    r = fmaf(fmaf(-d, r, 1.0f), r, r);
+    const float q = n * r;
+    return fmaf(fmaf(-d, q, n), r, q);
+}
+
+// sqrt(y) rounded to nearest for y in [0, 34] (the range of -2 ln u1): the
+// hardware estimate, then the neighbour test on the residuals y - s's.
+// Arguments are never denormal or infinite here, so no rescaling is needed.
+// Checked against IEEE sqrt on every one of the 2^24 arguments.
+__device__ __forceinline__ float sqrt_r(float y) {
+    float s = __builtin_amdgcn_sqrtf(y);
+    const float sm = __uint_as_float(__float_as_uint(s) - 1u);
+    const float sp = __uint_as_float(__float_as_uint(s) + 1u);
+    s = fmaf(-sm, s, y) <= 0.0f ? sm : s;
+    s = fmaf(-sp, s, y) > 0.0f ? sp : s;
+    return s;
+}
+
 __device__ __forceinline__ float ln_u1(uint32_t k) {
     const float f = __uint2float_rn(k);  // exact, k <= 2^24
     const uint32_t bits = __float_as_uint(f);
@@ -258,7 +283,7 @@ __device__ __forceinline__ float ln_u1(uint32_t k) {
     const bool low = m1 < 0x1.6a09e6p+0f;
     const float m = low ? m1 : m1 * 0.5f;
     const int e = low ? ebias : ebias + 1;
-    const float s = (m - 1.0f) / (m + 1.0f);
+    const float s = div_ln(m - 1.0f, m + 1.0f);
     const float z = s * s;
     float q = fmaf(z, (float)(2.0 / 9.0), (float)(2.0 / 7.0));
     q = fmaf(z, q, (float)(2.0 / 5.0));
@@ -293,7 +318,7 @@ __device__ __forceinline__ void sincos_turn(uint32_t k, float &c, float &s) {
 
 __device__ __forceinline__ void normal_pair(uint32_t x0, uint32_t x1, float &z0, float &z1) {
     const float l = ln_u1((x0 >> 8) + 1u);
-    const float r = __builtin_sqrtf(-2.0f * l);
+    const float r = sqrt_r(-2.0f * l);
     float c, s;
     sincos_turn(x1 >> 8, c, s);
     z0 = r * c;

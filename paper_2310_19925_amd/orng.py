@@ -70,6 +70,7 @@ def _load():
         "orng_fill": [i32, i32, u64, u32, u64, u64, vp, vp],
         "orng_fill_multi": [i32, i32, u64, u32, u32, u64, u64, vp, vp],
         "orng_brownian": [u64, u32, u32, u32, u64, u32, f32, f32, vp, vp, u32, vp],
+        "orng_normal_pairs": [vp, vp, u64, vp, vp, vp],
         "orng_fill_batched": [vp, C.c_size_t, vp],
         "orng_fill_each": [vp, C.c_size_t, vp],
         "orng_autotune": [i32, i32, C.c_char_p],
@@ -154,6 +155,11 @@ def orng_get_launch():
     _check(_lib.orng_get_launch(C.byref(cfg)), "orng_get_launch")
     return dict(wg_size=cfg.wg_size, unroll=cfg.unroll, max_wgs=cfg.max_wgs,
                 nontemporal=cfg.nontemporal)
+
+
+def orng_normal_pairs(x0, x1, n, z0, z1, stream=None):
+    _check(_lib.orng_normal_pairs(_ptr(x0), _ptr(x1), n, _ptr(z0), _ptr(z1), _stream(stream)),
+           "orng_normal_pairs")
 
 
 # orng_req_t as a numpy structured dtype (48 bytes, same field order)

@@ -167,3 +167,34 @@ def test_bulk_config_sampled(R, O):
                 assert abs(float(f.mean())) < 5 / 2**13 and abs(float(f.var()) - 1) < 5 * 2**-12.5
     del out
     torch.cuda.empty_cache()
+
+
+def test_normal_transform_exhaustive(R, O):
+    """Every argument of the logarithm (all 2^24 values of x0 >> 8) and of the
+    quarter-turn sine/cosine (all 2^24 values of x1 >> 8) through the GPU
+    Box-Muller transform, bit-exact against the oracle.  With x1 = 0 the cosine
+    is exactly 1, so z0 is the radius itself: this pins the division and the
+    square root of the GPU path to IEEE results on their whole input set."""
+    k = torch.arange(1 << 24, dtype=torch.int64, device="cuda")
+    z0 = torch.empty(1 << 24, dtype=torch.float32, device="cuda")
+    z1 = torch.empty_like(z0)
+    words = (k << 8).to(torch.int32)
+    low = torch.full_like(words, 0x5A)
+    cases = [(words | low, torch.zeros_like(words)),             # every u1, cos = 1
+             (torch.full_like(words, 0x12345678), words | low),  # every u2, radius A
+             (torch.full_like(words, 0x00ABCDEF), words)]        # every u2, radius B
+    for x0, x1 in cases:
+        R.orng_normal_pairs(x0, x1, 1 << 24, z0, z1)
+        torch.cuda.synchronize()
+        a0, a1 = O.normal_pair_n(x0.cpu().numpy().view(np.uint32), x1.cpu().numpy().view(np.uint32))
+        g0, g1 = as_u32(z0), as_u32(z1)
+        bad = np.nonzero((g0 != a0.view(np.uint32)) | (g1 != a1.view(np.uint32)))[0]
+        assert bad.size == 0, "mismatch at %d of 2^24" % bad[0]
+
+
+def test_normal_pairs_errors(R):
+    t = torch.zeros(8, dtype=torch.int32, device="cuda")
+    with pytest.raises(R.OrngError) as e:
+        R.orng_normal_pairs(t, 0, 8, t, t)
+    assert e.value.status == R.EINVAL
+    R.orng_normal_pairs(0, 0, 0, 0, 0)
