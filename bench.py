@@ -145,7 +145,7 @@ def _replay(orng, tr, idx, arena_bytes, open_loop):
     return st
 
 
-def bench_serve(orng, inputs, stream, dev):
+def bench_serve(orng, inputs, stream, dev, bulk_rates=None):
     """Poisson arrivals (mean 5,000/s) of mixed fill requests, sizes
     log-uniform in [2^10, 2^26] words, four generator families x three
     distributions, 32 GB arena: open-loop replay (latency) and saturated
@@ -174,6 +174,13 @@ def bench_serve(orng, inputs, stream, dev):
     torch.cuda.empty_cache()
     gs = lambda st: round(st["samples_done"] / st["first_submit_to_last_done_s"] / 1e9, 2)
     plain = words / (t_plain * 1e-3) / 1e9
+    extra = {}
+    if bulk_rates:
+        # the same samples at the bulk-fill rate of each request's (gen, dist)
+        t_bulk = sum(float(tr["n"][i]) / (bulk_rates[(int(tr["gen"][i]), int(tr["dist"][i]))] * 1e9)
+                     for i in range(m))
+        extra = {"bulk_rate_equiv_gsamples_s": round(words / t_bulk / 1e9, 2),
+                 "saturated_vs_bulk_rate": round(gs(sat) / (words / t_bulk / 1e9), 4)}
     return {"requests": int(m), "samples": words, "offered_req_per_s": 5000,
             "open_loop": {"p50_ms": round(op["latency_p50_ms"], 4),
                           "p99_ms": round(op["latency_p99_ms"], 4),
@@ -186,7 +193,7 @@ def bench_serve(orng, inputs, stream, dev):
                           "active_peak": sat["active_peak"],
                           "arena_peak_gb": round(sat["arena_peak_bytes"] / 1e9, 3)},
             "plain_each_gsamples_s": round(plain, 2),
-            "saturated_vs_plain": round(gs(sat) / plain, 4)}
+            "saturated_vs_plain": round(gs(sat) / plain, 4), **extra}
 
 
 def main():
@@ -303,7 +310,9 @@ def main():
         result["batched"] = bench_batched(orng, inputs, stream, dev)
 
     if not args.no_serve:
-        result["served"] = bench_serve(orng, inputs, stream, dev)
+        rates = {(g, d): k["gsamples_s"] for (g, d), k in zip(combos, kernels)}
+        result["served"] = bench_serve(orng, inputs, stream, dev,
+                                       rates if len(rates) == 15 else None)
 
     if not args.no_cpu:
         log("cpu baseline ...")

@@ -4,9 +4,10 @@
 // offset, n) exactly: a sample depends only on its own stream and position
 // (paper section 3.1), never on the other requests of the batch.
 //
-// Host: requests are validated, each is cut into tiles (the span of the fill
-// kernels: 64*U blocks of four words, or one Tyche tile), and a prefix sum
-// gives every request its first tile number.  The header, the request table
+// Host: requests are validated, each is cut into tiles of W consecutive spans
+// (a span is the fill kernels' unit: 64*U blocks of four words, or one Tyche
+// tile; W = waves per workgroup), and a prefix sum gives every request its
+// first tile number.  The header, the request table
 // and a tile -> request map are written into pinned staging and uploaded with
 // two copies into a device buffer whose layout is fixed for its capacity.
 // Device: a persistent grid pulls tiles from an atomic cursor in the header
@@ -45,7 +46,9 @@ struct BatchHdr {           // 64 bytes
     uint64_t cursor;        // next unclaimed tile; uploaded as 0 with the header
     uint32_t nreq;
     uint32_t chunk;
-    uint64_t pad[5];
+    uint32_t spans_per_tile;  // W: a tile is W consecutive spans of one request
+    uint32_t pad0;
+    uint64_t pad[4];
 };
 static_assert(sizeof(BatchHdr) == 64, "BatchHdr layout");
 
@@ -61,24 +64,25 @@ __device__ __forceinline__ uint64_t bcast_lane0(uint64_t x) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Generate tile t of the batch (wave-uniform t).
+// Generate spans j0, j0 + step, ... < W of tile t of the batch (wave-uniform).
 template <bool NT>
 __device__ __forceinline__ void run_tile(const DevReq *reqs, const uint32_t *map, uint64_t t,
-                                         uint32_t lane) {
+                                         uint32_t W, uint32_t j0, uint32_t step, uint32_t lane) {
     const uint32_t r = map[t];
     const DevReq q = reqs[r];
-    const uint64_t span = q.first_span + (t - q.tile_start);
     const KeySched ks = make_keysched(q.seed);
     const int gen = (int)(q.flags & 15u), dist = (int)((q.flags >> 4) & 15u);
-    process_span_any<NT>(gen, dist, ks, q.ctr, q.out, q.p0, q.p0 + q.n, span, q.unroll,
-                         (q.flags >> 8) & 3u, lane);
+    const uint64_t span0 = q.first_span + (t - q.tile_start) * W;
+    for (uint32_t j = j0; j < W; j += step)
+        process_span_any<NT>(gen, dist, ks, q.ctr, q.out, q.p0, q.p0 + q.n, span0 + j, q.unroll,
+                             (q.flags >> 8) & 3u, lane);
 }
 
 template <bool NT>
 __global__ __launch_bounds__(512) void k_batched(BatchView v) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t total = v.hdr->total_tiles;
-    const uint32_t chunk = v.hdr->chunk;
+    const uint32_t chunk = v.hdr->chunk, W = v.hdr->spans_per_tile;
     for (;;) {
         uint64_t t0 = 0;
         if (lane == 0)
@@ -87,19 +91,21 @@ __global__ __launch_bounds__(512) void k_batched(BatchView v) {
         t0 = bcast_lane0(t0);
         if (t0 >= total) break;
         const uint64_t t1 = t0 + chunk < total ? t0 + chunk : total;
-        for (uint64_t t = t0; t < t1; ++t) run_tile<NT>(v.reqs, v.map, t, lane);
+        for (uint64_t t = t0; t < t1; ++t) run_tile<NT>(v.reqs, v.map, t, W, 0, 1, lane);
     }
 }
 
-// Static schedule: wave w of the grid generates tile w (the grid is rounded up
-// to a size bucket so that a captured graph serves many batch sizes; waves
-// past the last tile exit at once).
+// Static schedule: workgroup t generates tile t, wave j of it span j of the
+// tile (W = waves per workgroup), so every wave is short-lived like the plain
+// fill's.  The grid is rounded up to a size bucket so that a captured graph
+// serves many batch sizes; workgroups past the last tile exit at once.
 template <bool NT>
 __global__ __launch_bounds__(512) void k_batched_static(BatchView v) {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t t = wave_uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const uint64_t t = blockIdx.x;
     if (t >= v.hdr->total_tiles) return;
-    run_tile<NT>(v.reqs, v.map, t, lane);
+    const uint32_t j = wave_uniform(threadIdx.x >> 6);
+    run_tile<NT>(v.reqs, v.map, t, blockDim.x >> 6, j, 0xFFFFu, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -175,11 +181,16 @@ static uint64_t bucket(uint64_t x) {
     return (x + step - 1) / step * step;
 }
 
+uint32_t batch_wg(int gen, int dist) {
+    const LaunchCfg cfg = launch_cfg();
+    return cfg.wg_size ? cfg.wg_size : tuned_fill(gen, dist).b_wg_size;
+}
+
 static BatchShape batch_shape(int gen, int dist, uint64_t tiles) {
     const Tuned tu = tuned_fill(gen, dist);
     const LaunchCfg cfg = launch_cfg();
     BatchShape s;
-    s.wg = cfg.wg_size ? cfg.wg_size : tu.b_wg_size;
+    s.wg = batch_wg(gen, dist);
     s.chunk = tu.b_chunk ? tu.b_chunk : 1;
     s.nt = false;
     const uint64_t wpg = s.wg / 64;
@@ -188,10 +199,10 @@ static BatchShape batch_shape(int gen, int dist, uint64_t tiles) {
     if (s.persistent) {
         uint64_t grid = (uint64_t)device_cu_count() * (tu.b_wgs_per_cu ? tu.b_wgs_per_cu : 4);
         if (cfg.max_wgs) grid = cfg.max_wgs;
-        const uint64_t need = (tiles + wpg - 1) / wpg;
+        const uint64_t need = (tiles + wpg - 1) / wpg;  // one tile per wave at a time
         s.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(grid, need));
     } else {
-        s.grid = (uint32_t)((bucket(tiles) + wpg - 1) / wpg);
+        s.grid = (uint32_t)bucket(tiles);  // one workgroup per tile
     }
     return s;
 }
@@ -212,13 +223,15 @@ int validate_request(const orng_req_t &r) {
     return ORNG_OK;
 }
 
-// Tile decomposition of one request with `unroll` blocks per lane.
-static void request_tiles(const orng_req_t &r, uint32_t unroll, uint64_t *first_span,
-                          uint64_t *count) {
+// Tile decomposition of one request: spans of `unroll` blocks per lane,
+// W spans per tile.
+void request_tiles(const orng_req_t &r, uint32_t unroll, uint32_t W, uint64_t *first_span,
+                   uint64_t *count) {
     const uint64_t sb = span_blocks((int)r.gen, unroll);
     const uint64_t fb = r.offset / 4, lb = (r.offset + r.n - 1) / 4;
     *first_span = fb / sb;
-    *count = lb / sb - *first_span + 1;
+    const uint64_t spans = lb / sb - *first_span + 1;
+    *count = (spans + W - 1) / W;
 }
 
 static bool use_graphs() {
@@ -243,11 +256,13 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     if (live.empty()) return ORNG_OK;
     std::vector<uint64_t> fspan(live.size()), cnt(live.size());
     std::vector<uint32_t> unr(live.size());
+    const orng_req_t &r0 = reqs[live[0]];
+    const uint32_t W = batch_wg((int)r0.gen, (int)r0.dist) / 64;
     uint64_t tiles = 0;
     for (size_t k = 0; k < live.size(); ++k) {
         const orng_req_t &r = reqs[live[k]];
         unr[k] = r.gen == ORNG_TYCHE ? 64 : tuned_fill((int)r.gen, (int)r.dist).b_unroll;
-        request_tiles(r, unr[k], &fspan[k], &cnt[k]);
+        request_tiles(r, unr[k], W, &fspan[k], &cnt[k]);
         tiles += cnt[k];
     }
     if (tiles > (1ull << 28)) return ORNG_ENOMEM;
@@ -265,7 +280,6 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     ORNG_TRY(ensure_capacity(c, live.size(), tiles));
     if (!db->capture) ORNG_TRY(hipStreamCreateWithFlags(&db->capture, hipStreamNonBlocking));
 
-    const orng_req_t &r0 = reqs[live[0]];
     const BatchShape sh = batch_shape((int)r0.gen, (int)r0.dist, tiles);
     size_t map_off;
     layout_bytes(c.cap_req, c.cap_tiles, &map_off);
@@ -277,6 +291,7 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     hdr->cursor = 0;
     hdr->nreq = (uint32_t)live.size();
     hdr->chunk = sh.chunk;
+    hdr->spans_per_tile = W;
     uint64_t ts = 0;
     for (size_t k = 0; k < live.size(); ++k) {
         const orng_req_t &r = reqs[live[k]];

@@ -36,9 +36,9 @@ static Tuned default_tuned(int gen, int dist) {
     t.max_wgs = 0;
     t.nontemporal = 2;
     t.b_wg_size = 256;
-    t.b_unroll = 16;
+    t.b_unroll = 4;
     t.b_chunk = 1;
-    t.b_wgs_per_cu = 8;
+    t.b_wgs_per_cu = 0;
     (void)dist;
     return t;
 }
@@ -226,11 +226,11 @@ int orng_autotune(int gen, int dist, const char *cache_path) {
     float best_b = 1e30f;
     Tuned bt = best;
     for (uint32_t wg : {128u, 256u, 512u})
-        for (uint32_t un : {2u, 4u, 8u, 16u, 32u, 64u})
-            for (uint32_t ch : {1u, 2u, 4u, 8u})
-                for (uint32_t wpc : {0u, 1u, 2u, 4u, 8u}) {  // 0: static schedule
+        for (uint32_t un : {1u, 2u, 4u, 8u, 16u})
+            for (uint32_t ch : {1u, 4u})
+                for (uint32_t wpc : {0u, 2u, 4u, 8u}) {  // 0: static schedule
                     if (e != hipSuccess) break;
-                    if (gen == G_TYCHE && un != 16) continue;
+                    if (gen == G_TYCHE && un != 1) continue;
                     if (wpc == 0 && ch != 1) continue;  // chunk is a queue parameter
                     Tuned t = best;
                     t.b_wg_size = wg;
