@@ -205,6 +205,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (counter calibration)")
+    ap.add_argument("--walk-steps", type=int, default=0, help="shorter walk (profiling runs)")
     ap.add_argument("--only", default="", help="gen:dist list to restrict the fills (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -219,6 +222,14 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+
+    if args.calib_copy:
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     seed = inputs.bulk_seed()
     n = inputs.BULK_N
@@ -283,7 +294,9 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_walk:
-        w = inputs.WALK
+        w = dict(inputs.WALK)
+        if args.walk_steps:
+            w["n_steps"], w["msd_every"] = args.walk_steps, max(1, args.walk_steps // 10)
         pos = torch.zeros((w["dim"], w["n_particles"]), dtype=torch.float32, device=dev)
         msd = torch.zeros(w["n_steps"] // w["msd_every"], dtype=torch.float64, device=dev)
         orng.orng_brownian(seed, 0, w["n_particles"], w["dim"], 0, 100, w["dt"], w["D"], pos,

@@ -112,18 +112,38 @@ __device__ __forceinline__ void tf4_block(uint32_t c0, uint32_t c1, const KeySch
 // Threefry2x64-20.  Counter (block, stream counter) as 64-bit words, key
 // (seed, 0); the block's four 32-bit words are lo X0, hi X0, lo X1, hi X1.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t rotl64(uint64_t x, int r) {
-    return (x << r) | (x >> (64 - r));
+// 64-bit rotate as two funnel shifts of the 32-bit halves (v_alignbit_b32):
+// for 0 < r < 32, hi' = (hi:lo) >> (32 - r) and lo' = (lo:hi) >> (32 - r);
+// r > 32 rotates the swapped halves by r - 32; r == 32 is the swap itself.
+template <int R>
+__device__ __forceinline__ uint64_t rotl64(uint64_t x) {
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    if constexpr (R == 32) {
+        return ((uint64_t)lo << 32) | hi;
+    } else if constexpr (R < 32) {
+        const uint32_t nh = __builtin_amdgcn_alignbit(hi, lo, 32 - R);
+        const uint32_t nl = __builtin_amdgcn_alignbit(lo, hi, 32 - R);
+        return ((uint64_t)nh << 32) | nl;
+    } else {
+        const uint32_t nh = __builtin_amdgcn_alignbit(lo, hi, 64 - R);
+        const uint32_t nl = __builtin_amdgcn_alignbit(hi, lo, 64 - R);
+        return ((uint64_t)nh << 32) | nl;
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void tf2_round(uint64_t &x0, uint64_t &x1) {
+    x0 += x1;
+    x1 = rotl64<R>(x1) ^ x0;
 }
 
 template <int S>
 __device__ __forceinline__ void tf2_quad(uint64_t &x0, uint64_t &x1, const KeySched &ks) {
     constexpr int ROT[8] = {16, 42, 12, 31, 16, 32, 24, 21};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        x0 += x1;
-        x1 = rotl64(x1, ROT[(4 * S - 4 + i) & 7]) ^ x0;
-    }
+    tf2_round<ROT[(4 * S - 4) & 7]>(x0, x1);
+    tf2_round<ROT[(4 * S - 3) & 7]>(x0, x1);
+    tf2_round<ROT[(4 * S - 2) & 7]>(x0, x1);
+    tf2_round<ROT[(4 * S - 1) & 7]>(x0, x1);
     x0 += ks.ks2[S % 3];
     x1 += ks.ks2[(S + 1) % 3] + (uint64_t)S;
 }

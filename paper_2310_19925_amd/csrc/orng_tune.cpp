@@ -29,17 +29,38 @@ static std::mutex g_tune_mu;
 static Tuned g_tuned[5][3];
 static bool g_tuned_init = false;
 
+// Measured on MI355X by orng_autotune (one entry per gen x dist, in
+// enum order): wg unroll max_wgs nontemporal | batched wg unroll chunk wgs/CU
+// (wgs/CU 0 = static one-workgroup-per-tile schedule).
+static const uint32_t kDefaultTable[15][8] = {
+        {256, 4, 0, 1, 512, 8, 1, 0},
+        {128, 8, 0, 1, 512, 16, 1, 0},
+        {128, 4, 8192, 1, 256, 16, 1, 0},
+        {256, 4, 8192, 1, 128, 16, 1, 0},
+        {512, 8, 8192, 1, 128, 16, 1, 0},
+        {256, 4, 8192, 2, 128, 8, 1, 0},
+        {256, 4, 8192, 2, 128, 16, 1, 0},
+        {128, 4, 8192, 1, 256, 16, 1, 0},
+        {256, 4, 8192, 1, 128, 16, 1, 0},
+        {256, 4, 8192, 1, 256, 8, 1, 0},
+        {128, 4, 8192, 1, 256, 16, 1, 0},
+        {256, 2, 8192, 1, 256, 16, 1, 0},
+        {512, 64, 0, 2, 512, 1, 1, 0},
+        {512, 64, 8192, 2, 256, 1, 1, 0},
+        {512, 64, 2048, 2, 128, 1, 1, 0},
+};
+
 static Tuned default_tuned(int gen, int dist) {
+    const uint32_t *v = kDefaultTable[gen * 3 + dist];
     Tuned t;
-    t.wg_size = 256;
-    t.unroll = (gen == G_TYCHE) ? 64 : 1;
-    t.max_wgs = 0;
-    t.nontemporal = 2;
-    t.b_wg_size = 256;
-    t.b_unroll = 4;
-    t.b_chunk = 1;
-    t.b_wgs_per_cu = 0;
-    (void)dist;
+    t.wg_size = v[0];
+    t.unroll = v[1];
+    t.max_wgs = v[2];
+    t.nontemporal = v[3];
+    t.b_wg_size = v[4];
+    t.b_unroll = v[5];
+    t.b_chunk = v[6];
+    t.b_wgs_per_cu = v[7];
     return t;
 }
 
