@@ -30,6 +30,39 @@ HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
 INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # full-rate 32-bit VALU lane-ops/s
 
 
+# HBM traffic per launch of each bulk fill from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE, KiB per dispatch; see profiles/), with the
+# calibration factors a 1 GiB device copy gives for each counter.  Valid only
+# for the kernel sources they were measured on: bench.py reports null traffic
+# when the hash of those sources differs.
+TRAFFIC_SRC_SHA = "0df11ddf88ea9f23"
+TRAFFIC_FACTORS = (1.999921324963899, 1.0)  # FETCH, WRITE
+TRAFFIC_KIB = {
+    (0, 0): (64.5625, 4194596.375), (0, 1): (33.0, 4195048.0), (0, 2): (88.875, 4194317.0),
+    (1, 0): (35.625, 4194317.5), (1, 1): (33.5, 4194309.125), (1, 2): (42.5, 4194304.0),
+    (2, 0): (32.5, 4194304.0), (2, 1): (32.5, 4194304.5), (2, 2): (41.0, 4194304.125),
+    (3, 0): (33.5, 4195420.75), (3, 1): (35.0, 4194304.75), (3, 2): (41.5, 4194304.125),
+    (4, 0): (64.0625, 4194304.0), (4, 1): (35.1875, 4194304.0), (4, 2): (38.0625, 4194304.0),
+}
+
+
+def fill_sources_sha():
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2310_19925_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "orng_device.hpp")) +
+                   glob.glob(os.path.join(csrc, "orng_span.hpp")) +
+                   glob.glob(os.path.join(csrc, "orng_fill.hip")))
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in files)).hexdigest()[:16]
+
+
+def traffic_bytes(gen, dist):
+    if fill_sources_sha() != TRAFFIC_SRC_SHA or (gen, dist) not in TRAFFIC_KIB:
+        return None
+    f, w = TRAFFIC_KIB[(gen, dist)]
+    return round(f * 1024 * TRAFFIC_FACTORS[0] + w * 1024 * TRAFFIC_FACTORS[1])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -100,6 +133,19 @@ def bench_batched(orng, inputs, stream, dev):
     half = total // 2
     t_plain = _time_events(stream, lambda: orng.orng_fill_multi(0, 0, 42, 0, 2, 0, half, buf,
                                                                  stream), 5)
+    # host time of one batched call (validation, tiling, staging, enqueue)
+    torch.cuda.synchronize()
+    h0 = time.perf_counter()
+    orng.orng_fill_batched(reqs, stream)
+    t_host = (time.perf_counter() - h0) * 1e3
+    torch.cuda.synchronize()
+    # back-to-back calls: host preparation of call k+1 overlaps call k on the device
+    K = 8
+    t_batched_pipe = _time_events(stream, lambda: [orng.orng_fill_batched(reqs, stream)
+                                                   for _ in range(K)], 3) / K
+    t_plain_pipe = _time_events(stream, lambda: [orng.orng_fill_multi(0, 0, 42, 0, 2, 0, half,
+                                                                      buf, stream)
+                                                 for _ in range(K)], 3) / K
     del buf
     torch.cuda.empty_cache()
     g = lambda ms, words: round(words / (ms * 1e-3) / 1e9, 2)
@@ -108,7 +154,13 @@ def bench_batched(orng, inputs, stream, dev):
             "each_ms": round(t_each, 3), "each_gsamples_s": g(t_each, total),
             "plain_ms": round(t_plain, 3), "plain_gsamples_s": g(t_plain, 2 * half),
             "batched_vs_plain": round(t_plain / t_batched * total / (2 * half), 4),
-            "batched_vs_each": round(t_each / t_batched, 2)}
+            "batched_vs_each": round(t_each / t_batched, 2),
+            "batched_host_ms": round(t_host, 3),
+            "pipelined": {"batched_ms": round(t_batched_pipe, 3),
+                          "plain_ms": round(t_plain_pipe, 3),
+                          "batched_gsamples_s": g(t_batched_pipe, total),
+                          "batched_vs_plain": round(t_plain_pipe / t_batched_pipe * total
+                                                    / (2 * half), 4)}}
 
 
 def _replay(orng, tr, idx, arena_bytes, open_loop):
@@ -272,8 +324,10 @@ def main():
     dom = max(range(len(combos)), key=lambda k: per_kernel_ms[k])
     dk = kernels[dom]
     roofline = {"bound": "hbm", "achieved": dk["write_gbs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": dk["hbm_frac"], "traffic": None,
-                "kernel": "%s/%s" % (dk["gen"], dk["dist"])}
+                "unit": "GB/s", "frac": dk["hbm_frac"],
+                "traffic": traffic_bytes(*combos[dom]),
+                "kernel": "%s/%s" % (dk["gen"], dk["dist"]),
+                "algorithmic_bytes": 4 * n}
     total_ms = sum(per_kernel_ms)
     step_hbm_frac = (4.0 * n * len(combos) / (total_ms * 1e-3) / 1e9) / HBM_PEAK_GBS
 

@@ -258,10 +258,13 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     std::vector<uint32_t> unr(live.size());
     const orng_req_t &r0 = reqs[live[0]];
     const uint32_t W = batch_wg((int)r0.gen, (int)r0.dist) / 64;
+    uint32_t unroll_of[5][3];  // one table lookup per pair, not per request
+    for (int g = 0; g < 5; ++g)
+        for (int d = 0; d < 3; ++d) unroll_of[g][d] = g == G_TYCHE ? 64 : tuned_fill(g, d).b_unroll;
     uint64_t tiles = 0;
     for (size_t k = 0; k < live.size(); ++k) {
         const orng_req_t &r = reqs[live[k]];
-        unr[k] = r.gen == ORNG_TYCHE ? 64 : tuned_fill((int)r.gen, (int)r.dist).b_unroll;
+        unr[k] = unroll_of[r.gen][r.dist];
         request_tiles(r, unr[k], W, &fspan[k], &cnt[k]);
         tiles += cnt[k];
     }
@@ -308,7 +311,7 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
         const uint32_t delta = (uint32_t)((addr_words - r.offset) & 3u);
         d.flags = r.gen | (r.dist << 4) | (delta << 8);
         d.pad = 0;
-        for (uint64_t t = 0; t < cnt[k]; ++t) map[ts + t] = (uint32_t)k;
+        std::fill_n(map + ts, cnt[k], (uint32_t)k);
         ts += cnt[k];
     }
     ORNG_TRY(hipMemcpyAsync(c.d_buf, c.h_buf, sizeof(BatchHdr) + live.size() * sizeof(DevReq),
