@@ -1,0 +1,143 @@
+"""Host-side logic of liborng that runs without a GPU: argument validation of
+every entry point (errors are returned before any device work), the
+launch-knob checks and the launch-table file loader."""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2310_19925_amd", "liborng.so")
+EINVAL, ERANGE, ENOMEM, ENOENT = -1, -2, -3, -7
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(LIB):
+        pytest.fail("liborng.so not built")
+    lib = C.CDLL(LIB)
+    u32, u64, i32, vp, f32 = C.c_uint32, C.c_uint64, C.c_int, C.c_void_p, C.c_float
+    lib.orng_fill.argtypes = [i32, i32, u64, u32, u64, u64, vp, vp]
+    lib.orng_fill_multi.argtypes = [i32, i32, u64, u32, u32, u64, u64, vp, vp]
+    lib.orng_brownian.argtypes = [u64, u32, u32, u32, u64, u32, f32, f32, vp, vp, u32, vp]
+    lib.orng_normal_pairs.argtypes = [vp, vp, u64, vp, vp, vp]
+    lib.orng_fill_batched.argtypes = [vp, C.c_size_t, vp]
+    lib.orng_fill_each.argtypes = [vp, C.c_size_t, vp]
+    lib.orng_tune_load.argtypes = [C.c_char_p]
+    lib.orng_autotune.argtypes = [i32, i32, C.c_char_p]
+    lib.orng_serve_create.argtypes = [vp, C.POINTER(vp)]
+    return lib
+
+
+FAKE = 0x10000  # a non-null, 16-byte aligned address that is never dereferenced
+
+
+def test_fill_validation(L):
+    assert L.orng_fill(-1, 0, 1, 1, 0, 4, FAKE, None) == EINVAL
+    assert L.orng_fill(0, 3, 1, 1, 0, 4, FAKE, None) == EINVAL
+    assert L.orng_fill(0, 0, 1, 1, 2**32 - 3, 4, FAKE, None) == ERANGE
+    assert L.orng_fill(0, 0, 1, 1, 2**32 + 1, 0, FAKE, None) == ERANGE
+    assert L.orng_fill(0, 0, 1, 1, 0, 4, FAKE + 2, None) == EINVAL
+    assert L.orng_fill(0, 0, 1, 1, 0, 4, None, None) == EINVAL
+    assert L.orng_fill(0, 0, 1, 1, 2**32, 0, None, None) == 0
+
+
+def test_fill_multi_validation(L):
+    assert L.orng_fill_multi(0, 0, 1, 2**32 - 2, 3, 0, 4, FAKE, None) == ERANGE
+    assert L.orng_fill_multi(0, 0, 1, 2**32 - 3, 3, 2**32 - 1, 2, FAKE, None) == ERANGE
+    assert L.orng_fill_multi(0, 0, 1, 0, 0, 0, 4, None, None) == 0
+    assert L.orng_fill_multi(0, 0, 1, 0, 5, 0, 0, None, None) == 0
+    assert L.orng_fill_multi(7, 0, 1, 0, 5, 0, 4, FAKE, None) == EINVAL
+
+
+def test_brownian_validation(L):
+    assert L.orng_brownian(1, 0, 4, 0, 0, 1, 1e-3, 1.0, FAKE, None, 0, None) == EINVAL
+    assert L.orng_brownian(1, 0, 4, 4, 0, 1, 1e-3, 1.0, FAKE, None, 0, None) == EINVAL
+    assert L.orng_brownian(1, 0, 4, 3, 0, 1, 1e-3, -1.0, FAKE, None, 0, None) == EINVAL
+    assert L.orng_brownian(1, 0, 4, 3, 0, 1, float("nan"), 1.0, FAKE, None, 0, None) == EINVAL
+    assert L.orng_brownian(1, 0, 4, 3, 2**32 // 3, 2, 1e-3, 1.0, FAKE, None, 0, None) == ERANGE
+    assert L.orng_brownian(1, 2**32 - 2, 4, 3, 0, 2, 1e-3, 1.0, FAKE, None, 0, None) == ERANGE
+    assert L.orng_brownian(1, 0, 4, 3, 0, 1, 1e-3, 1.0, None, None, 0, None) == EINVAL
+    assert L.orng_brownian(1, 0, 4, 3, 0, 1, 1e-3, 1.0, FAKE, FAKE + 4, 1, None) == EINVAL
+    assert L.orng_brownian(1, 0, 0, 3, 0, 1, 1e-3, 1.0, None, None, 0, None) == 0
+
+
+def test_normal_pairs_validation(L):
+    assert L.orng_normal_pairs(FAKE, None, 4, FAKE, FAKE, None) == EINVAL
+    assert L.orng_normal_pairs(FAKE, FAKE + 1, 4, FAKE, FAKE, None) == EINVAL
+    assert L.orng_normal_pairs(None, None, 0, None, None, None) == 0
+
+
+def _reqs(rows):
+    dt = np.dtype([("seed", "<u8"), ("offset", "<u8"), ("n", "<u8"), ("out", "<u8"),
+                   ("ctr", "<u4"), ("gen", "<u4"), ("dist", "<u4"), ("flags", "<u4")])
+    r = np.zeros(len(rows), dt)
+    for i, (gen, dist, off, n, out, flags) in enumerate(rows):
+        r[i] = (1, off, n, out, 2, gen, dist, flags)
+    return r
+
+
+@pytest.mark.parametrize("fn", ["orng_fill_batched", "orng_fill_each"])
+def test_batched_validation_rejects_whole_batch(L, fn):
+    f = getattr(L, fn)
+    cases = [
+        ([(0, 0, 0, 16, FAKE, 0), (5, 0, 0, 16, FAKE, 0)], EINVAL),     # bad generator
+        ([(0, 4, 0, 16, FAKE, 0)], EINVAL),                              # bad distribution
+        ([(0, 0, 0, 16, FAKE, 1)], EINVAL),                              # reserved flags
+        ([(0, 0, 2**32 - 8, 16, FAKE, 0)], ERANGE),                      # past the period
+        ([(0, 0, 0, 16, 0, 0)], EINVAL),                                 # NULL output
+        ([(0, 0, 0, 16, FAKE + 2, 0)], EINVAL),                          # misaligned output
+    ]
+    for rows, want in cases:
+        r = _reqs(rows)
+        assert f(r.ctypes.data, r.size, None) == want, rows
+    empty = _reqs([(0, 0, 0, 0, 0, 0)])
+    assert f(empty.ctypes.data, 1, None) == 0  # nothing to do
+    assert f(None, 0, None) == 0
+    assert f(None, 3, None) == EINVAL
+
+
+def test_launch_knob_validation(L):
+    class cfg_t(C.Structure):
+        _fields_ = [("wg_size", C.c_uint32), ("unroll", C.c_uint32), ("max_wgs", C.c_uint32),
+                    ("nontemporal", C.c_uint32)]
+    L.orng_set_launch.argtypes = [C.POINTER(cfg_t)]
+    L.orng_get_launch.argtypes = [C.POINTER(cfg_t)]
+    assert L.orng_set_launch(C.byref(cfg_t(100, 0, 0, 0))) == EINVAL
+    assert L.orng_set_launch(C.byref(cfg_t(1024, 0, 0, 0))) == EINVAL
+    assert L.orng_set_launch(C.byref(cfg_t(64, 65, 0, 0))) == EINVAL
+    assert L.orng_set_launch(C.byref(cfg_t(64, 2, 0, 3))) == EINVAL
+    assert L.orng_set_launch(C.byref(cfg_t(128, 2, 7, 1))) == 0
+    got = cfg_t()
+    assert L.orng_get_launch(C.byref(got)) == 0
+    assert (got.wg_size, got.unroll, got.max_wgs, got.nontemporal) == (128, 2, 7, 1)
+    assert L.orng_set_launch(None) == 0
+    assert L.orng_get_launch(C.byref(got)) == 0 and got.wg_size == 0
+    assert L.orng_get_launch(None) == EINVAL
+
+
+def test_tune_table_loader(L, tmp_path):
+    assert L.orng_tune_load(str(tmp_path / "missing.txt").encode()) == ENOENT
+    bad = tmp_path / "bad.txt"
+    bad.write_text("# header\n0 0 100 4 0 1 256 4 1 0\n9 0 256 4 0 1 256 4 1 0\nnot numbers\n")
+    assert L.orng_tune_load(str(bad).encode()) == EINVAL  # no valid line
+    good = tmp_path / "good.txt"
+    good.write_text("# header\n0 0 256 2 0 2 256 4 1 0\n4 1 256 64 0 2 256 1 1 0\n")
+    assert L.orng_tune_load(str(good).encode()) == 0
+    assert L.orng_autotune(5, 0, None) == EINVAL
+
+
+def test_serve_create_validation(L):
+    class cfg_t(C.Structure):
+        _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_uint64),
+                    ("max_slots", C.c_uint32), ("flags", C.c_uint32),
+                    ("step_words", C.c_uint64)]
+    h = C.c_void_p()
+    assert L.orng_serve_create(None, C.byref(h)) == EINVAL
+    assert L.orng_serve_create(C.cast(C.pointer(cfg_t(None, 0, 0, 0, 0)), C.c_void_p),
+                               C.byref(h)) == EINVAL
+    assert L.orng_serve_create(C.cast(C.pointer(cfg_t(None, 1 << 20, 0, 1, 0)), C.c_void_p),
+                               C.byref(h)) == EINVAL
+    assert L.orng_serve_create(C.cast(C.pointer(cfg_t(FAKE + 8, 1 << 20, 0, 0, 0)), C.c_void_p),
+                               C.byref(h)) == EINVAL
