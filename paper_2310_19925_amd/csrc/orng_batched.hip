@@ -97,12 +97,14 @@ __global__ __launch_bounds__(512) void k_batched(BatchView v) {
 
 // Static schedule: workgroup t generates tile t, wave j of it span j of the
 // tile (W = waves per workgroup), so every wave is short-lived like the plain
-// fill's.  The grid is rounded up to a size bucket so that a captured graph
-// serves many batch sizes; workgroups past the last tile exit at once.
+// fill's.  The grid is rounded up to a size bucket (a multiple of the XCD
+// count) so that a captured graph serves many batch sizes; workgroups past the
+// last tile exit at once.  Each XCD takes a contiguous range of tiles, so the
+// tile map and request rows it reads stay in its own L2.
 template <bool NT>
 __global__ __launch_bounds__(512) void k_batched_static(BatchView v) {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t t = blockIdx.x;
+    const uint64_t t = xcd_tile(blockIdx.x, gridDim.x);
     if (t >= v.hdr->total_tiles) return;
     const uint32_t j = wave_uniform(threadIdx.x >> 6);
     run_tile<NT>(v.reqs, v.map, t, blockDim.x >> 6, j, 0xFFFFu, lane);
@@ -202,7 +204,7 @@ static BatchShape batch_shape(int gen, int dist, uint64_t tiles) {
         const uint64_t need = (tiles + wpg - 1) / wpg;  // one tile per wave at a time
         s.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(grid, need));
     } else {
-        s.grid = (uint32_t)bucket(tiles);  // one workgroup per tile
+        s.grid = (uint32_t)((bucket(tiles) + XCDS - 1) / XCDS * XCDS);  // one workgroup per tile
     }
     return s;
 }
