@@ -179,14 +179,24 @@ def _replay(orng, tr, idx, arena_bytes, open_loop):
             orng.orng_serve_wait(srv, tickets[k])
             orng.orng_serve_release(srv, tickets[k])
 
+    if not open_loop:
+        # every request arrives at t = 0: one submission of all of them, and the
+        # client releases each result as soon as it is done
+        reqs = orng.make_requests(tr["gen"][idx], tr["dist"][idx], tr["seed"][idx],
+                                  tr["ctr"][idx], tr["offset"][idx], tr["n"][idx], 0)
+        all_t = orng.orng_serve_submit_many(srv, reqs)
+        for k in range(0, len(all_t), 64):
+            orng.orng_serve_release_many(srv, all_t[k:k + 64])
+        st = orng.orng_serve_stats(srv)
+        orng.orng_serve_destroy(srv)
+        return st
     th = threading.Thread(target=releaser)
     th.start()
     t0 = time.perf_counter()
     for k, i in enumerate(idx):
-        if open_loop:
-            dt = t0 + float(tr["t"][i]) - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
+        dt = t0 + float(tr["t"][i]) - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
         tickets[k] = orng.orng_serve_submit(srv, int(tr["gen"][i]), int(tr["dist"][i]),
                                             int(tr["seed"][i]), int(tr["ctr"][i]),
                                             int(tr["offset"][i]), int(tr["n"][i]))

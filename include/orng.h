@@ -229,6 +229,16 @@ int orng_serve_create(const orng_serve_cfg_t *cfg, orng_server_t **srv);
    caller's buffer is written.  Errors: EINVAL/ERANGE (as orng_fill), ENOMEM
    (output larger than the arena), EBUSY (server shutting down). */
 int orng_serve_submit(orng_server_t *srv, const orng_req_t *req, uint64_t *ticket);
+/* Queue n requests in one call (one arrival of many); tickets[i] receives the
+   ticket of reqs[i].  All requests are validated first: on an error nothing is
+   queued and the status is that of the first bad request. */
+int orng_serve_submit_many(orng_server_t *srv, const orng_req_t *reqs, size_t n,
+                           uint64_t *tickets);
+/* Wait for each of tickets[0 .. n) in order and release it as soon as it is
+   done (up to timeout_ns in total, < 0: forever).  *released (nullable) gets
+   how many were released; EBUSY on timeout, ENOENT at an unknown ticket. */
+int orng_serve_release_many(orng_server_t *srv, const uint64_t *tickets, size_t n,
+                            int64_t timeout_ns, size_t *released);
 /* ORNG_OK and *res when done, ORNG_EBUSY while queued or running, ENOENT for
    unknown or released tickets. */
 int orng_serve_poll(orng_server_t *srv, uint64_t ticket, orng_result_t *res);

@@ -7,7 +7,7 @@
 // stream (seed, ctr0 + i); global step g uses normal samples dim*g .. dim*g +
 // dim - 1 of that stream; each coordinate is updated as
 // x = fmaf(sigma, normal, x), sigma = float(sqrt(2 D dt)).  One Philox block
-// yields four normals, so three blocks cover four 3-D steps.  Positions are
+// yields four normals, so three blocks cover four 3-D steps (a group).  Positions are
 // read once and written once (12 bytes per particle for the 3-D case); the
 // only other memory traffic is the optional mean-squared-displacement
 // snapshot, a workgroup reduction plus one float64 atomic per workgroup.
@@ -43,43 +43,81 @@ __device__ void wg_sum_add(double v, double *dst) {
     __syncthreads();
 }
 
+// Normal sample q of this lane's stream (one Philox block, one pair).
+__device__ __forceinline__ float normal_at(uint64_t q, uint32_t ctr, const KeySched &ks) {
+    uint32_t w[4];
+    philox_block((uint32_t)(q >> 2), ctr, ks, w);
+    const uint32_t h = (uint32_t)(q >> 1) & 1u;
+    float z0, z1;
+    normal_pair(h ? w[2] : w[0], h ? w[3] : w[1], z0, z1);
+    return (q & 1) ? z1 : z0;
+}
+
+// Per-step bookkeeping shared by both loops: count local steps and take an
+// MSD snapshot after every msd_every of them (uniform across the grid).
+template <int DIM>
+__device__ __forceinline__ void after_step(const WalkArgs &a, const float x[DIM], bool live,
+                                           uint32_t &done, uint32_t &next_snap) {
+    ++done;
+    if (a.msd_every && done == next_snap) {
+        double r2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) r2 += (double)x[e] * (double)x[e];
+        wg_sum_add(live ? r2 : 0.0, a.msd + (done / a.msd_every - 1));
+        next_snap += a.msd_every;
+    }
+}
+
+// Steps are processed in groups that start on a Philox block boundary:
+// GB blocks (4*GB normals) feed GS = 4*GB/DIM whole steps, so inside a group
+// every normal's coordinate is a compile-time constant.  Steps before the
+// first group boundary and after the last are done one at a time.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
+    constexpr uint32_t GB = DIM == 3 ? 3 : 1;   // Philox blocks per group
+    constexpr uint32_t GS = 4 * GB / DIM;       // steps per group
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = i < a.n;
     float x[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) x[d] = live ? a.pos[(uint64_t)d * a.n + i] : 0.0f;
     const uint32_t ctr = a.ctr0 + i;
-    const uint64_t step0 = a.q0 / DIM;
-    // blocks of four normals covering [q0, q1)
-    const uint64_t bfirst = a.q0 / 4, blast = (a.q1 - 1) / 4;
-    for (uint64_t b = bfirst; b <= blast; ++b) {
-        uint32_t w[4];
-        philox_block((uint32_t)b, ctr, a.ks, w);
-        float g[4];
-        normal_pair(w[0], w[1], g[0], g[1]);
-        normal_pair(w[2], w[3], g[2], g[3]);
-        const bool inner = b * 4 >= a.q0 && b * 4 + 4 <= a.q1;
-        const uint32_t d0 = (uint32_t)((b * 4) % DIM);
+    const uint64_t g0 = a.q0 / DIM, g1 = a.q1 / DIM;  // global steps [g0, g1)
+    uint64_t ga = (g0 + GS - 1) / GS * GS;             // first group-aligned step
+    if (ga > g1) ga = g1;
+    const uint64_t gb = ga + (g1 - ga) / GS * GS;      // end of whole groups
+    uint32_t done = 0, next_snap = a.msd_every;
+    // head: single steps
+    for (uint64_t g = g0; g < ga; ++g) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint64_t q = b * 4 + (uint64_t)j;
-            if (!inner && (q < a.q0 || q >= a.q1)) continue;
-            const uint32_t d = (d0 + (uint32_t)j) % DIM;  // wave-uniform
+        for (int d = 0; d < DIM; ++d)
+            x[d] = fmaf(a.sigma, normal_at(DIM * g + d, ctr, a.ks), x[d]);
+        after_step<DIM>(a, x, live, done, next_snap);
+    }
+    // whole groups
+    for (uint64_t g = ga; g < gb; g += GS) {
+        const uint64_t b0 = DIM * g / 4;
+        float nrm[4 * GB];
 #pragma unroll
-            for (int e = 0; e < DIM; ++e)
-                if ((uint32_t)e == d) x[e] = fmaf(a.sigma, g[j], x[e]);
-            if (a.msd_every && d == DIM - 1) {
-                const uint64_t done = q / DIM + 1 - step0;  // local steps completed
-                if (done % a.msd_every == 0) {
-                    double r2 = 0.0;
-#pragma unroll
-                    for (int e = 0; e < DIM; ++e) r2 += (double)x[e] * (double)x[e];
-                    wg_sum_add(live ? r2 : 0.0, a.msd + (done / a.msd_every - 1));
-                }
-            }
+        for (uint32_t k = 0; k < GB; ++k) {
+            uint32_t w[4];
+            philox_block((uint32_t)(b0 + k), ctr, a.ks, w);
+            normal_pair(w[0], w[1], nrm[4 * k + 0], nrm[4 * k + 1]);
+            normal_pair(w[2], w[3], nrm[4 * k + 2], nrm[4 * k + 3]);
         }
+#pragma unroll
+        for (uint32_t s = 0; s < GS; ++s) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) x[d] = fmaf(a.sigma, nrm[DIM * s + d], x[d]);
+            after_step<DIM>(a, x, live, done, next_snap);
+        }
+    }
+    // tail: single steps
+    for (uint64_t g = gb; g < g1; ++g) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            x[d] = fmaf(a.sigma, normal_at(DIM * g + d, ctr, a.ks), x[d]);
+        after_step<DIM>(a, x, live, done, next_snap);
     }
     if (live) {
 #pragma unroll

@@ -77,6 +77,8 @@ def _load():
         "orng_tune_load": [C.c_char_p],
         "orng_serve_create": [C.POINTER(orng_serve_cfg_t), C.POINTER(C.c_void_p)],
         "orng_serve_submit": [vp, C.POINTER(orng_req_t), C.POINTER(C.c_uint64)],
+        "orng_serve_submit_many": [vp, vp, C.c_size_t, vp],
+        "orng_serve_release_many": [vp, vp, C.c_size_t, C.c_int64, C.POINTER(C.c_size_t)],
         "orng_serve_poll": [vp, u64, C.POINTER(orng_result_t)],
         "orng_serve_wait": [vp, u64, C.c_int64, C.POINTER(orng_result_t)],
         "orng_serve_release": [vp, u64],
@@ -218,6 +220,30 @@ def orng_serve_submit(srv, gen, dist, seed, ctr, offset, n, out=None):
     t = C.c_uint64()
     _check(_lib.orng_serve_submit(srv, C.byref(r), C.byref(t)), "orng_serve_submit")
     return t.value
+
+
+def orng_serve_submit_many(srv, reqs):
+    """reqs: numpy array of orng_req_t records (make_requests; out = 0 asks for
+    an arena output).  Returns a numpy array of tickets."""
+    import numpy as np
+    assert reqs.dtype.itemsize == 48 and reqs.flags["C_CONTIGUOUS"]
+    t = np.zeros(reqs.size, dtype=np.uint64)
+    _check(_lib.orng_serve_submit_many(srv, reqs.ctypes.data if reqs.size else None, reqs.size,
+                                       t.ctypes.data if reqs.size else None),
+           "orng_serve_submit_many")
+    return t
+
+
+def orng_serve_release_many(srv, tickets, timeout_ns=-1):
+    """Wait for and release tickets in order; returns how many were released."""
+    import numpy as np
+    t = np.ascontiguousarray(tickets, dtype=np.uint64)
+    n = C.c_size_t()
+    st = _lib.orng_serve_release_many(srv, t.ctypes.data if t.size else None, t.size, timeout_ns,
+                                      C.byref(n))
+    if st not in (OK, EBUSY):
+        _check(st, "orng_serve_release_many")
+    return n.value
 
 
 def _result(res):

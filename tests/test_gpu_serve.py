@@ -173,3 +173,30 @@ def test_serve_destroy_drains_in_flight(R, O):
     for k in range(8):
         ref = O.fill(4, 1, k, k, 0, 1 << 17).view(np.uint32)
         assert np.array_equal(host[k * (1 << 17):(k + 1) * (1 << 17)], ref)
+
+
+def test_serve_submit_many_and_release_many(R, O):
+    rng = np.random.default_rng(7)
+    qs = _random_reqs(rng, 50)
+    arena = _arena(16 << 20)
+    srv = R.orng_serve_create(arena.numel() * 4, arena=arena)
+    try:
+        reqs = R.make_requests([q["gen"] for q in qs], [q["dist"] for q in qs],
+                               [q["seed"] for q in qs], [q["ctr"] for q in qs],
+                               [q["offset"] for q in qs], [q["n"] for q in qs], 0)
+        tickets = R.orng_serve_submit_many(srv, reqs)
+        assert len(set(tickets.tolist())) == 50
+        for q, t in zip(qs[:10], tickets[:10]):
+            res = R.orng_serve_wait(srv, int(t))
+            ref = O.fill(q["gen"], q["dist"], q["seed"], q["ctr"], q["offset"], q["n"])
+            assert np.array_equal(_read(arena, res), ref.view(np.uint32))
+        assert R.orng_serve_release_many(srv, tickets) == 50
+        st = R.orng_serve_stats(srv)
+        assert st["released"] == 50 and st["completed"] == 50
+        bad = R.make_requests([0, 9], 0, 1, 1, 0, 16, 0)
+        with pytest.raises(R.OrngError) as e:
+            R.orng_serve_submit_many(srv, bad)
+        assert e.value.status == R.EINVAL
+        assert R.orng_serve_stats(srv)["submitted"] == 50  # nothing of the bad batch queued
+    finally:
+        R.orng_serve_destroy(srv)
