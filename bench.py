@@ -325,12 +325,17 @@ def main():
     value = total_samples / wall / 1e9
     ms_per_step = wall / args.steps * 1e3
 
+    # measured store-only ceiling: a plain store kernel (torch's fill) on the same buffer
+    t_store = _time_events(stream, lambda: out.fill_(0), 5)
+    ceiling_gbs = 4.0 * n / (t_store * 1e-3) / 1e9
+
     kernels = []
     for (g, d), ms in zip(combos, per_kernel_ms):
         gbs = 4.0 * n / (ms * 1e-3) / 1e9
         kernels.append({"gen": inputs.GEN_NAMES[g], "dist": inputs.DIST_NAMES[d],
                         "ms": round(ms, 4), "gsamples_s": round(n / (ms * 1e-3) / 1e9, 2),
-                        "write_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+                        "write_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "store_ceiling_frac": round(gbs / ceiling_gbs, 4)})
     dom = max(range(len(combos)), key=lambda k: per_kernel_ms[k])
     dk = kernels[dom]
     roofline = {"bound": "hbm", "achieved": dk["write_gbs"], "peak": HBM_PEAK_GBS,
@@ -351,6 +356,7 @@ def main():
                    "samples_per_fill": n, "fills_per_step": len(combos),
                    "parallelism": "single GPU"},
         "hbm_write_frac_step": round(step_hbm_frac, 4),
+        "store_ceiling_gbs": round(ceiling_gbs, 1),
         "roofline": roofline,
         "kernels": kernels,
     }
