@@ -35,14 +35,14 @@ INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # full-rate 32-bit VALU lane-ops/s
 # calibration factors a 1 GiB device copy gives for each counter.  Valid only
 # for the kernel sources they were measured on: bench.py reports null traffic
 # when the hash of those sources differs.
-TRAFFIC_SRC_SHA = "0df11ddf88ea9f23"
-TRAFFIC_FACTORS = (1.999921324963899, 1.0)  # FETCH, WRITE
+TRAFFIC_SRC_SHA = "8ff78c0fcb673050"
+TRAFFIC_FACTORS = (1.9999225169637187, 1.0)  # FETCH, WRITE
 TRAFFIC_KIB = {
-    (0, 0): (64.5625, 4194596.375), (0, 1): (33.0, 4195048.0), (0, 2): (88.875, 4194317.0),
-    (1, 0): (35.625, 4194317.5), (1, 1): (33.5, 4194309.125), (1, 2): (42.5, 4194304.0),
-    (2, 0): (32.5, 4194304.0), (2, 1): (32.5, 4194304.5), (2, 2): (41.0, 4194304.125),
-    (3, 0): (33.5, 4195420.75), (3, 1): (35.0, 4194304.75), (3, 2): (41.5, 4194304.125),
-    (4, 0): (64.0625, 4194304.0), (4, 1): (35.1875, 4194304.0), (4, 2): (38.0625, 4194304.0),
+    (0, 0): (65.25, 4194349.875), (0, 1): (32.9375, 4195287.875), (0, 2): (80.3125, 4194314.0),
+    (1, 0): (55.0, 4194322.625), (1, 1): (33.5, 4194308.125), (1, 2): (43.0, 4194304.0),
+    (2, 0): (34.625, 4194304.0), (2, 1): (33.625, 4194327.0), (2, 2): (42.1875, 4194304.875),
+    (3, 0): (34.4375, 4194938.875), (3, 1): (35.0625, 4194323.875), (3, 2): (42.3125, 4194307.5),
+    (4, 0): (75.4375, 4194304.0), (4, 1): (29.0, 4194304.0), (4, 2): (36.5, 4194304.0),
 }
 
 
