@@ -34,6 +34,12 @@ struct KeySched {
     uint32_t seed_lo, seed_hi;
 };
 
+// a ^ b ^ c in one gfx950 v_bitop3_b32 (truth table 0x96: the output bit is
+// the parity of the three input bits).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10.  Counter (c0, c1, 0, 0): c0 is the block number inside the
 // stream, c1 the stream counter.  The two zero words make the first round's
@@ -46,8 +52,8 @@ __device__ __forceinline__ void philox_block(uint32_t c0, uint32_t c1, const Key
     for (int r = 0; r < 10; ++r) {
         const uint64_t a = (uint64_t)x0 * 0xD2511F53u;
         const uint64_t b = (uint64_t)x2 * 0xCD9E8D57u;
-        const uint32_t n0 = (uint32_t)(b >> 32) ^ x1 ^ ks.k[r][0];
-        const uint32_t n2 = (uint32_t)(a >> 32) ^ x3 ^ ks.k[r][1];
+        const uint32_t n0 = xor3((uint32_t)(b >> 32), x1, ks.k[r][0]);
+        const uint32_t n2 = xor3((uint32_t)(a >> 32), x3, ks.k[r][1]);
         x1 = (uint32_t)b;
         x3 = (uint32_t)a;
         x0 = n0;
