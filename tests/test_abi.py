@@ -48,3 +48,34 @@ def test_host_only_calls_without_gpu():
     assert lib.orng_fill(0, 0, 1, 1, 2**32, 1, None, None) == -2
     assert lib.orng_fill(0, 0, 1, 1, 0, 0, None, None) == 0
     assert lib.orng_fill(0, 0, 1, 1, 0, 4, None, None) == -1
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/orng.h compiles as C99 and a C program links against liborng.so
+    and calls the host-only entry points."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if not gcc:
+        pytest.skip("gcc not available")
+    src = tmp_path / "t.c"
+    src.write_text(
+        '#include "orng.h"\n#include <stdio.h>\n'
+        'int main(void) {\n'
+        '  orng_req_t r = {0};\n'
+        '  orng_launch_t l = {0};\n'
+        '  orng_serve_stats_t st;\n'
+        '  (void)r; (void)st;\n'
+        '  if (orng_get_launch(&l) != ORNG_OK) return 1;\n'
+        '  if (orng_fill(ORNG_TYCHE + 1, ORNG_U32, 1, 1, 0, 4, (void*)0, (void*)0) != ORNG_EINVAL) return 2;\n'
+        '  printf("%s %d\\n", orng_strerror(ORNG_ERANGE), orng_version());\n'
+        '  return sizeof(orng_req_t) == 48 ? 0 : 3;\n'
+        '}\n')
+    exe = tmp_path / "t"
+    libdir = os.path.dirname(LIB)
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), LIB, "-Wl,-rpath," + libdir, "-o", str(exe)],
+                   check=True, capture_output=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    assert r.stdout.startswith("position or counter out of range")

@@ -200,3 +200,36 @@ def test_serve_submit_many_and_release_many(R, O):
         assert R.orng_serve_stats(srv)["submitted"] == 50  # nothing of the bad batch queued
     finally:
         R.orng_serve_destroy(srv)
+
+
+def test_serve_trace_requests_sampled(R, O):
+    """The first 400 requests of the serving workload (Poisson arrivals,
+    sizes log-uniform in [2^10, 2^26] words, all generator families and
+    distributions), submitted at once into a 16 GiB arena and checked on
+    sampled positions (first, last and random words) against the oracle."""
+    from paper_2310_19925_amd import inputs
+    tr = inputs.serve_trace()
+    m = 400
+    assert int(tr["n"][:m].sum()) * 4 < (16 << 30)
+    arena = _arena(16 << 30)
+    srv = R.orng_serve_create(arena.numel() * 4, arena=arena)
+    rng = np.random.default_rng(9)
+    try:
+        reqs = R.make_requests(tr["gen"][:m], tr["dist"][:m], tr["seed"][:m], tr["ctr"][:m],
+                               tr["offset"][:m], tr["n"][:m], 0)
+        tickets = R.orng_serve_submit_many(srv, reqs)
+        for i, t in enumerate(tickets):
+            res = R.orng_serve_wait(srv, int(t))
+            n = int(tr["n"][i])
+            js = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, 6)]))
+            off = (res["d_out"] - arena.data_ptr()) // 4
+            got = arena[torch.from_numpy(off + js).cuda()].cpu().numpy().view(np.uint32)
+            ref = O.samples_at(int(tr["gen"][i]), int(tr["dist"][i]), int(tr["seed"][i]),
+                               np.full(js.size, tr["ctr"][i], np.uint32),
+                               (int(tr["offset"][i]) + js).astype(np.uint64))
+            assert np.array_equal(got, ref.view(np.uint32)), ("request", i)
+        assert R.orng_serve_release_many(srv, tickets) == m
+    finally:
+        R.orng_serve_destroy(srv)
+    del arena
+    torch.cuda.empty_cache()
