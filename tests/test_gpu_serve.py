@@ -233,3 +233,15 @@ def test_serve_trace_requests_sampled(R, O):
         R.orng_serve_destroy(srv)
     del arena
     torch.cuda.empty_cache()
+
+
+def test_serve_destroy_with_unreleased_results_still_drains(R):
+    """Finished results that the client never released fill the arena; destroy
+    still runs the queued requests (their outputs die with the server)."""
+    arena = _arena(1 << 20)
+    srv = R.orng_serve_create(arena.numel() * 4, arena=arena)
+    ts = [R.orng_serve_submit(srv, 0, 0, i, i, 0, 200_000) for i in range(3)]
+    assert R.orng_serve_wait(srv, ts[0]) is not None
+    t0 = time.time()
+    R.orng_serve_destroy(srv)  # must not wait for a release that never comes
+    assert time.time() - t0 < 60
