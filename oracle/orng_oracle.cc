@@ -58,8 +58,13 @@ void philox_round(uint32_t x[4], const uint32_t k[2]) {
  * Key schedule: four key words plus their XOR with the Skein parity constant.
  * The key is injected before round 0 and after every fourth round, with the
  * injection number added to the last word.  Rotation pairs repeat with
- * period 8; even rounds mix (0,1),(2,3), odd rounds mix (0,3),(2,1).
- * Pinned: rocRAND's Threefry4x32-20 rounds on random keys/counters.
+ * period 8; even rounds mix (0,1),(2,3), odd rounds mix (0,3),(2,1) (the
+ * Threefish word permutation after every round).
+ * Pinned in two steps: rocRAND's Threefry4x32-20 switches mixing pairs every
+ * second round, so a big-integer transcription run with rocRAND's schedule
+ * is checked against rocRAND (rotations, key schedule, parity constant,
+ * injections), and the same transcription with the schedule above is checked
+ * against this function.
  * ------------------------------------------------------------------------- */
 const unsigned TF4_ROT[8][2] = {{10, 26}, {11, 21}, {13, 27}, {23, 5},
                                 {6, 20},  {17, 11}, {25, 10}, {18, 20}};
