@@ -185,7 +185,7 @@ int orng_tune_load(const char *cache_path);
  * allocates, and a table of device-resident slots holding the stream state of
  * every admitted request (seed, counter, position range, output).  Requests
  * are admitted in arrival order as slots and arena space free up; each device
- * step generates tiles of all admitted requests in one launch, and up to two
+ * step generates tiles of all admitted requests in one launch, and up to three
  * steps are in flight, so requests that arrive while others run join the next
  * step and their work overlaps on the device.  Results are bit-identical to
  * orng_fill of the same request, alone or in any mix.
