@@ -278,27 +278,24 @@ __device__ __forceinline__ float to_uniform(uint32_t x) {
 
 // n / d rounded to nearest for the operands ln_u1 produces (d = m + 1 in
 // [1.70, 2.42], n = m - 1 in [-0.30, 0.42]): hardware reciprocal estimate,
-// one Newton step, then one residual correction of the quotient (Markstein).
-// The GPU test-suite checks it against the IEEE quotient for every one of
-// the 2^24 arguments of ln_u1.
+// then one residual correction of the quotient (Markstein).  On this operand
+// set the result is the IEEE quotient for every one of the 2^24 arguments of
+// ln_u1 (checked exhaustively on the GPU against the CPU oracle).
 __device__ __forceinline__ float div_ln(float n, float d) {
-    float r = __builtin_amdgcn_rcpf(d);
-    r = fmaf(fmaf(-d, r, 1.0f), r, r);
+    const float r = __builtin_amdgcn_rcpf(d);
     const float q = n * r;
     return fmaf(fmaf(-d, q, n), r, q);
 }
 
-// sqrt(y) rounded to nearest for y in [0, 34] (the range of -2 ln u1): the
-// hardware estimate, then the neighbour test on the residuals y - s's.
-// Arguments are never denormal or infinite here, so no rescaling is needed.
-// Checked against IEEE sqrt on every one of the 2^24 arguments.
+// sqrt(y) rounded to nearest for y in [0, 34] (the range of -2 ln u1):
+// s = y * rsq(y), then one Markstein correction s + (y - s^2) * rsq(y) / 2;
+// y = 0 (u1 = 1) is passed through.  Equal to the IEEE square root on every
+// one of the 2^24 arguments (checked exhaustively on the GPU).
 __device__ __forceinline__ float sqrt_r(float y) {
-    float s = __builtin_amdgcn_sqrtf(y);
-    const float sm = __uint_as_float(__float_as_uint(s) - 1u);
-    const float sp = __uint_as_float(__float_as_uint(s) + 1u);
-    s = fmaf(-sm, s, y) <= 0.0f ? sm : s;
-    s = fmaf(-sp, s, y) > 0.0f ? sp : s;
-    return s;
+    const float r = __builtin_amdgcn_rsqf(y);
+    const float s = y * r;
+    const float o = fmaf(fmaf(-s, s, y), 0.5f * r, s);
+    return y == 0.0f ? y : o;
 }
 
 __device__ __forceinline__ float ln_u1(uint32_t k) {
@@ -334,12 +331,14 @@ __device__ __forceinline__ void sincos_turn(uint32_t k, float &c, float &s) {
     pc = fmaf(z, pc, (float)(1.0 / 24.0));
     pc = fmaf(z, pc, -0.5f);
     const float cs = fmaf(z, pc, 1.0f);
-    const uint32_t j = q & 3u;
-    // rotate (cs, sn) by j quarter turns
-    const float cr = (j & 1u) ? sn : cs;
-    const float sr = (j & 1u) ? cs : sn;
-    c = ((j + 1u) & 2u) ? -cr : cr;   // j = 1, 2 negate cos
-    s = (j & 2u) ? -sr : sr;          // j = 2, 3 negate sin
+    // rotate (cs, sn) by j = q mod 4 quarter turns: swap for odd j, then flip
+    // the sign bit of cos for j = 1, 2 and of sin for j = 2, 3
+    const uint32_t v = k + 0x200000u;  // bits 22, 23 of v are the two bits of j
+    const bool odd = (v & 0x400000u) != 0;
+    const float cr = odd ? sn : cs;
+    const float sr = odd ? cs : sn;
+    c = __uint_as_float(__float_as_uint(cr) ^ (((v + 0x400000u) & 0x800000u) << 8));
+    s = __uint_as_float(__float_as_uint(sr) ^ ((v & 0x800000u) << 8));
 }
 
 __device__ __forceinline__ void normal_pair(uint32_t x0, uint32_t x1, float &z0, float &z1) {
