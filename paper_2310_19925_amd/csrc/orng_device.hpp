@@ -169,29 +169,43 @@ __device__ __forceinline__ void tf2_block(uint32_t c0, uint32_t c1, const KeySch
 
 // ---------------------------------------------------------------------------
 // Squares32: counter ((stream counter << 32) | position), key from the seed.
-// x*x + a mod 2^64 is built from one 32x32 low product and one
-// v_mad_u64_u32: x*x = xl*xl + 2*xl*xh*2^32 (mod 2^64), and the low word of
-// (2*xl*xh) << 32 is zero, so the add of a only needs a carry-free high add.
+// x*x + a mod 2^64 = (xl*xl + a) + 2*xl*xh*2^32: one v_mad_u64_u32 for the
+// first sum, and the cross term only touches the high word (its low word is
+// zero), so it is a 32-bit multiply and a shift-add.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t sq_add(uint64_t x, uint64_t a) {
-    const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
-    const uint32_t cross = xl * xh;
-    const uint64_t addend = a + ((uint64_t)(cross + cross) << 32);
-    return (uint64_t)xl * xl + addend;
+__device__ __forceinline__ void sq_add(uint32_t xl, uint32_t xh, uint64_t a,
+                                       uint32_t &rl, uint32_t &rh) {
+    const uint64_t t = (uint64_t)xl * xl + a;
+    rl = (uint32_t)t;
+    rh = (uint32_t)(t >> 32) + 2u * (xl * xh);
 }
 
-__device__ __forceinline__ uint64_t swap32(uint64_t x) { return (x >> 32) | (x << 32); }
+// Four rounds on y = ((ctr << 32) | pos) * key and z = y + key (mod 2^64);
+// each round squares, adds, and swaps the 32-bit halves (the swap is a
+// renaming of the result words).
+__device__ __forceinline__ uint32_t squares_rounds(uint64_t y, uint64_t z) {
+    uint32_t l, h;
+    sq_add((uint32_t)y, (uint32_t)(y >> 32), y, l, h);  // round 1: x = y
+    sq_add(h, l, z, l, h);                              // round 2
+    sq_add(h, l, y, l, h);                              // round 3
+    sq_add(h, l, z, l, h);                              // round 4: output the high word
+    return h;
+}
 
-__device__ __forceinline__ uint32_t squares_word(uint32_t ctr, uint32_t pos, uint64_t key) {
-    // y = ((ctr << 32) | pos) * key mod 2^64
+// Words of positions 4*blk .. 4*blk+3.  y is affine in the position, so
+// y(p+1) = y(p) + key = z(p): after one full product per block, every further
+// y and z is one 64-bit add.
+__device__ __forceinline__ void squares_block(uint32_t blk, uint32_t ctr, uint64_t key,
+                                              uint32_t w[4]) {
+    const uint32_t p = blk << 2;
     const uint32_t kl = (uint32_t)key, kh = (uint32_t)(key >> 32);
-    const uint32_t hi_add = pos * kh + ctr * kl;
-    const uint64_t y = (uint64_t)pos * kl + ((uint64_t)hi_add << 32);
-    const uint64_t z = y + key;
-    uint64_t x = swap32(sq_add(y, y));
-    x = swap32(sq_add(x, z));
-    x = swap32(sq_add(x, y));
-    return (uint32_t)(sq_add(x, z) >> 32);
+    uint64_t y = (uint64_t)p * kl + ((uint64_t)(p * kh + ctr * kl) << 32);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t z = y + key;
+        w[i] = squares_rounds(y, z);
+        y = z;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -262,7 +276,7 @@ constexpr uint32_t TYCHE_TILE_BLOCKS = 4096;
 // float32 conversions.
 //   uniform  : (x >> 8) * 2^-24, exact, in [0, 1 - 2^-24].
 //   ln_u1(k) : ln(k * 2^-24) for k in [1, 2^24]: k = m 2^e with m in
-//              [sqrt(1/2), sqrt(2)) read from the float's bits, ln m =
+//              [sqrt(1/2), sqrt(2)) split off with integer arithmetic on the float's bits, ln m =
 //              2 atanh(s), s = (m-1)/(m+1), series to s^9, then the exponent
 //              part with a two-piece ln 2 (high piece exact times e-24).
 //   sincos   : cos, sin of 2 pi k/2^24 for k in [0, 2^24): nearest quarter
@@ -301,11 +315,12 @@ __device__ __forceinline__ float sqrt_r(float y) {
 __device__ __forceinline__ float ln_u1(uint32_t k) {
     const float f = __uint2float_rn(k);  // exact, k <= 2^24
     const uint32_t bits = __float_as_uint(f);
-    const int ebias = (int)(bits >> 23) - 127;
-    const float m1 = __uint_as_float((bits & 0x007FFFFFu) | 0x3F800000u);  // [1, 2)
-    const bool low = m1 < 0x1.6a09e6p+0f;
-    const float m = low ? m1 : m1 * 0.5f;
-    const int e = low ? ebias : ebias + 1;
+    // f = m 2^e with m in [sqrt(1/2), sqrt(2)): subtracting the bits of the
+    // float nearest sqrt(1/2) (0x3F3504F3) borrows from the exponent exactly
+    // when the fraction is below that of sqrt(2), so the shifted difference is
+    // e, and removing e from the exponent field leaves m
+    const int e = (int)(bits - 0x3F3504F3u) >> 23;
+    const float m = __uint_as_float(bits - ((uint32_t)e << 23));
     const float s = div_ln(m - 1.0f, m + 1.0f);
     const float z = s * s;
     float q = fmaf(z, (float)(2.0 / 9.0), (float)(2.0 / 7.0));
@@ -375,10 +390,8 @@ __device__ __forceinline__ void counter_block(uint32_t blk, uint32_t ctr, const 
         tf4_block(blk, ctr, ks, w);
     } else if constexpr (G == G_TF2X64) {
         tf2_block(blk, ctr, ks, w);
-    } else {  // G_SQUARES: four independent words
-        const uint32_t p = blk << 2;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) w[i] = squares_word(ctr, p + (uint32_t)i, ks.sqkey);
+    } else {  // G_SQUARES
+        squares_block(blk, ctr, ks.sqkey, w);
     }
 }
 
