@@ -27,7 +27,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
-INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # full-rate 32-bit VALU lane-ops/s
+# VALU issue peak: 256 CUs x 64 lanes x 2.4 GHz full-rate 32-bit lane operations
+# ("slots") per second.
+VALU_PEAK_TSLOTS = 256 * 64 * 2.4e9 / 1e12
+
+# Algorithmic VALU slots per sample of each generator and distribution.  The
+# operations the definitions require, written with the shortest gfx950 encoding
+# of each (64-bit add, 32x32->64 product-add, three-input xor or add, funnel
+# rotate: one instruction each); work on values uniform across a wave (keys,
+# the stream counter) runs on the scalar unit and is not counted; an fp32
+# operation counts half a slot (the published 157.3 TFLOP/s vector rate is two
+# fp32 operations per lane and clock), a reciprocal or reciprocal square root
+# one.  Every choice undercounts rather than overcounts.
+#   Philox4x32-10: 10 rounds x (2 products + 2 xor3), round 1 half uniform: 38 / 4 words
+#   Threefry4x32-20: 18 full rounds x 6 + rounds 1-2 (2 + 5) + counter add 1
+#     + injections 4 x 2 (x0, x2 fold into the next round's add) + final 4: 128 / 4 words
+#   Threefry2x64-20: 19 rounds x (add 1 + rotate 2 + xor 2) + round 1 (3) + counter add 1
+#     + 5 injections x 2 adds: 109 / 4 words
+#   Squares32: 4 rounds x (product-add, low product, shift-add) + 1 add (y -> z) per
+#     word, one full y product (3) per 4 words
+#   Tyche: one MIX (4 add, 4 xor, 4 rotate) per word + 20 MIX per 256 words (lane init)
+#   f32 uniform: shift + convert + scale = 1 + 2 x 0.5
+#   f32 normal, per pair: 16 integer ops, 37 fp32 ops, rcp + rsq = 36.5 slots
+SLOTS_GEN = {0: 38 / 4, 1: 128 / 4, 2: 109 / 4, 3: 13 + 3 / 4, 4: 12 + 20 * 12 / 256}
+SLOTS_DIST = {0: 0.0, 1: 2.0, 2: 36.5 / 2}
+
+
+def roofs(gen, dist, n, ms):
+    """HBM and VALU roofline fractions of one fill launch; the binding roof is
+    the one whose model time is longer."""
+    t = ms * 1e-3
+    slots = (SLOTS_GEN[gen] + SLOTS_DIST[dist]) * n
+    t_hbm = 4.0 * n / (HBM_PEAK_GBS * 1e9)
+    t_alu = slots / (VALU_PEAK_TSLOTS * 1e12)
+    return {"valu_tslots_s": round(slots / t / 1e12, 2), "valu_frac": round(t_alu / t, 4),
+            "binding": "alu" if t_alu > t_hbm else "hbm",
+            "binding_frac": round(max(t_alu, t_hbm) / t, 4), "slots": slots}
 
 
 # HBM traffic per launch of each bulk fill from two rocprofv3 --pmc passes
@@ -332,17 +367,28 @@ def main():
     kernels = []
     for (g, d), ms in zip(combos, per_kernel_ms):
         gbs = 4.0 * n / (ms * 1e-3) / 1e9
+        rf = roofs(g, d, n, ms)
         kernels.append({"gen": inputs.GEN_NAMES[g], "dist": inputs.DIST_NAMES[d],
                         "ms": round(ms, 4), "gsamples_s": round(n / (ms * 1e-3) / 1e9, 2),
                         "write_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                        "store_ceiling_frac": round(gbs / ceiling_gbs, 4)})
+                        "store_ceiling_frac": round(gbs / ceiling_gbs, 4),
+                        "valu_tslots_s": rf["valu_tslots_s"], "valu_frac": rf["valu_frac"],
+                        "binding": rf["binding"], "binding_frac": rf["binding_frac"]})
+    # the dominant (longest) kernel of the step, against its binding roof
     dom = max(range(len(combos)), key=lambda k: per_kernel_ms[k])
     dk = kernels[dom]
-    roofline = {"bound": "hbm", "achieved": dk["write_gbs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": dk["hbm_frac"],
-                "traffic": traffic_bytes(*combos[dom]),
-                "kernel": "%s/%s" % (dk["gen"], dk["dist"]),
-                "algorithmic_bytes": 4 * n}
+    drf = roofs(*combos[dom], n, per_kernel_ms[dom])
+    common = {"traffic": traffic_bytes(*combos[dom]),
+              "kernel": "%s/%s" % (dk["gen"], dk["dist"]), "algorithmic_bytes": 4 * n,
+              "algorithmic_valu_slots": round(drf["slots"]),
+              "hbm": {"achieved": dk["write_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": dk["hbm_frac"]}}
+    if drf["binding"] == "alu":
+        roofline = {"bound": "alu", "achieved": drf["valu_tslots_s"], "peak": VALU_PEAK_TSLOTS,
+                    "unit": "Tslots/s", "frac": drf["valu_frac"], **common}
+    else:
+        roofline = {"bound": "hbm", "achieved": dk["write_gbs"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": dk["hbm_frac"], **common}
     total_ms = sum(per_kernel_ms)
     step_hbm_frac = (4.0 * n * len(combos) / (total_ms * 1e-3) / 1e9) / HBM_PEAK_GBS
 
