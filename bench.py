@@ -68,8 +68,8 @@ def roofs(gen, dist, n, ms):
 # HBM traffic per launch of each bulk fill from two rocprofv3 --pmc passes
 # (FETCH_SIZE, WRITE_SIZE, KiB per dispatch; see profiles/), with the
 # calibration factors a 1 GiB device copy gives for each counter.  Valid only
-# for the kernel sources they were measured on: bench.py reports null traffic
-# when the hash of those sources differs.
+# for the kernel sources and launch table they were measured on: bench.py
+# reports null traffic when the hash of those sources differs.
 TRAFFIC_SRC_SHA = "8ff78c0fcb673050"
 TRAFFIC_FACTORS = (1.9999225169637187, 1.0)  # FETCH, WRITE
 TRAFFIC_KIB = {
@@ -87,7 +87,8 @@ def fill_sources_sha():
     csrc = os.path.join(ROOT, "paper_2310_19925_amd", "csrc")
     files = sorted(glob.glob(os.path.join(csrc, "orng_device.hpp")) +
                    glob.glob(os.path.join(csrc, "orng_span.hpp")) +
-                   glob.glob(os.path.join(csrc, "orng_fill.hip")))
+                   glob.glob(os.path.join(csrc, "orng_fill.hip")) +
+                   glob.glob(os.path.join(csrc, "orng_tune.cpp")))
     return hashlib.sha256(b"".join(open(f, "rb").read() for f in files)).hexdigest()[:16]
 
 

@@ -169,8 +169,10 @@ int orng_fill_each(const orng_req_t *h_reqs, size_t nreq, void *stream);
  * orng_autotune -- time launch variants of the fill and batched kernels for
  * (gen, dist) on the current device (workgroup size, blocks of four words per
  * lane per tile, tiles per queue claim, persistent workgroups per CU) and keep
- * the fastest; results never change, only speed.  Allocates about 1 GiB of
- * device memory for the duration of the call and synchronizes the device.
+ * the fastest (a first pass over all variants, then the fastest few and the
+ * entry in use re-timed against each other in interleaved rounds); results
+ * never change, only speed.  Allocates 4 GiB of device memory for the
+ * duration of the call and synchronizes the device.
  * cache_path (nullable): text file that receives the table of tuned entries
  * (existing entries for other pairs are kept).  orng_tune_load reads such a
  * file; the library also reads $ORNG_TUNE_CACHE at first use.
