@@ -73,6 +73,9 @@ def lib():
             "oracle_walk_sigma": (f32, [f32, f32]),
             "oracle_brownian": (i32, [u64, u32, vp, u32, u32, u64, u32, f32, f32, vp, vp, u32,
                                       i32]),
+            "oracle_u01_f64": (C.c_double, [u32, u32]),
+            "oracle_bd2": (i32, [u64, vp, u32, u32, u32, C.c_double, C.c_double, vp, vp, vp, vp,
+                                 i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -249,3 +252,27 @@ def brownian(seed, ctr0, n_particles=None, ids=None, dim=3, step0=0, n_steps=1, 
     if rc != 0:
         raise ValueError("oracle_brownian rejected arguments (%d)" % rc)
     return pos, msd
+
+
+def u01_f64(w0, w1):
+    return lib().oracle_u01_f64(int(w0) & 0xFFFFFFFF, int(w1) & 0xFFFFFFFF)
+
+
+def bd2(pid0, n_particles=None, ids=None, step0=1, n_steps=1, dt=1e-3, c=1.0, state=None,
+        nthreads=None):
+    """The paper's 2-D Brownian dynamics example.  state: (x, y, vx, vy)
+    float64 arrays of `count` entries (zeros when None).  Returns the updated
+    copy as a (4, count) float64 array."""
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        count = ids.size
+    else:
+        count = n_particles
+    st = np.zeros((4, count), np.float64) if state is None else \
+        np.ascontiguousarray(np.asarray(state, np.float64).reshape(4, count)).copy()
+    rc = lib().oracle_bd2(pid0, ids.ctypes.data if ids is not None else None, count, step0,
+                          n_steps, dt, c, st[0].ctypes.data, st[1].ctypes.data,
+                          st[2].ctypes.data, st[3].ctypes.data, nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_bd2 rejected arguments (%d)" % rc)
+    return st

@@ -3,8 +3,9 @@
  *
  * A plain, slow, obviously-correct CPU implementation of everything the
  * counter-based generation path computes: the four generator families, the
- * stream-to-block mapping, the float32 conversions, the Box-Muller normal and
- * the fused Brownian walk.  Only the test-suite, the smoke check and the CPU
+ * stream-to-block mapping, the float32 conversions, the Box-Muller normal,
+ * the fused Brownian walk, the float64 uniform and the paper's own 2-D
+ * Brownian dynamics example.  Only the test-suite, the smoke check and the CPU
  * baseline leg of the benchmark may load it.  The product library never
  * links, includes or calls anything here, and nothing here includes the
  * product's headers: the two are independent transcriptions of the same
@@ -88,6 +89,18 @@ float oracle_walk_sigma(float dt, float D);
 int oracle_brownian(uint64_t seed, uint32_t ctr0, const uint32_t *ids, uint32_t count,
                     uint32_t dim, uint64_t step0, uint32_t n_steps, float dt, float D,
                     float *pos, double *msd, uint32_t msd_every, int nthreads);
+
+/* --- the paper's 2-D Brownian dynamics (section 4, Fig. 1) ---------------- */
+/* float64 uniform in [0, 1) from two consecutive words of a stream (w0 at the
+   even position): the top 53 bits of (w1 << 32 | w0) times 2^-53 */
+double oracle_u01_f64(uint32_t w0, uint32_t w1);
+/* n_steps steps of the paper's example for particles pid0 + (ids ? ids[k] : k),
+   k < count; state arrays x, y, vx, vy (count entries each, float64) are
+   updated in place.  c = gamma / mass.  Returns 0, or -2 if a counter
+   step0 + s would pass 2^32 - 1. */
+int oracle_bd2(uint64_t pid0, const uint32_t *ids, uint32_t count, uint32_t step0,
+               uint32_t n_steps, double dt, double c, double *x, double *y, double *vx,
+               double *vy, int nthreads);
 
 #ifdef __cplusplus
 }
