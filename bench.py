@@ -10,7 +10,9 @@ output resident in HBM.  Per-kernel durations come from HIP events recorded on
 the launch stream around every launch of the timed steps.
 
 Also reported (same JSON line): the fused Brownian walk (2^24 particles, 3-D,
-10^4 steps) in steps/s, and the CPU oracle on a bounded sample of the same
+10^4 steps) in steps/s; the paper's 2-D Brownian dynamics run (10^6
+particles, 10^4 steps, float64) fused and with one launch per step; the
+batched and served paths; and the CPU oracle on a bounded sample of the same
 fill workload as the CPU baseline.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-walk] [--no-cpu]
@@ -243,6 +245,51 @@ def _replay(orng, tr, idx, arena_bytes, open_loop):
     return st
 
 
+# VALU slots per particle-step of the paper's 2-D Brownian dynamics: one
+# Philox block (round 1 on the zero counter words folds to one xor3; 9 rounds
+# x (2 product-adds + 2 xor3): 37; the per-lane key schedule depends only on
+# the particle and is formed once per launch, not per step) and 26 float64
+# operations (two 53-bit conversions of 4 each; drag, kick and move, 9 per
+# component).  The published 78.6 TFLOP/s float64 vector rate is one
+# operation per lane and clock, so each is one slot.
+BD2_SLOTS = 37 + 26
+BD2_BYTES_PER_STEP = 64  # one launch per step: load and store x, y, vx, vy
+
+
+def bench_bd2(orng, inputs, stream, dev):
+    """The paper's 2-D Brownian dynamics run (10^6 particles, 10^4 steps):
+    all steps in one launch vs one launch per step (the paper's structure)."""
+    import torch
+    p = inputs.BD2
+    n, T = p["n"], p["n_steps"]
+    st = torch.zeros((4, n), dtype=torch.float64, device=dev)
+
+    def run(spl):
+        st.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        orng.orng_bd2(p["pid0"], n, p["step0"], T, p["dt"], p["gamma_over_m"], st[0], st[1],
+                      st[2], st[3], spl, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    orng.orng_bd2(p["pid0"], n, p["step0"], 10, p["dt"], p["gamma_over_m"], st[0], st[1], st[2],
+                  st[3], 1, stream)  # warm-up
+    fused = min(run(0) for _ in range(2))
+    per_step = run(1)
+    ps = n * T
+    slots = BD2_SLOTS * ps
+    del st
+    return {"n_particles": n, "n_steps": T, "fused_ms": round(fused, 3),
+            "per_step_launch_ms": round(per_step, 3),
+            "fused_particle_steps_per_s": round(ps / (fused * 1e-3), 1),
+            "fused_vs_per_step": round(per_step / fused, 3),
+            "fused_valu_tslots_s": round(slots / (fused * 1e-3) / 1e12, 2),
+            "fused_valu_frac": round(slots / (fused * 1e-3) / 1e12 / VALU_PEAK_TSLOTS, 4),
+            "per_step_gbs": round(BD2_BYTES_PER_STEP * ps / (per_step * 1e-3) / 1e9, 1)}
+
+
 def bench_serve(orng, inputs, stream, dev, bulk_rates=None):
     """Poisson arrivals (mean 5,000/s) of mixed fill requests, sizes
     log-uniform in [2^10, 2^26] words, four generator families x three
@@ -303,6 +350,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-bd2", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (counter calibration)")
     ap.add_argument("--walk-steps", type=int, default=0, help="shorter walk (profiling runs)")
@@ -435,6 +483,9 @@ def main():
                           "msd_last": round(m[-1], 5),
                           "msd_expected_last": 2 * w["dim"] * w["D"] * w["n_steps"] * w["dt"]}
         del pos, msd
+
+    if not args.no_bd2:
+        result["bd2"] = bench_bd2(orng, inputs, stream, dev)
 
     if not args.no_batched:
         result["batched"] = bench_batched(orng, inputs, stream, dev)

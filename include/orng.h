@@ -118,6 +118,32 @@ int orng_brownian(uint64_t seed, uint32_t ctr0, uint32_t n_particles, uint32_t d
                   double *d_msd, uint32_t msd_every, void *stream);
 
 /*
+ * orng_bd2 -- the paper's 2-D Brownian dynamics example (section 4, Fig. 1,
+ * run as the GPU benchmark of section 5.1), in float64.
+ * Particle i (0 <= i < n) has id pid = pid0 + i, which is its generator's
+ * seed; step s (s < n_steps) uses counter step0 + s.  Per step, with r.x from
+ * words 0, 1 and r.y from words 2, 3 of Philox4x32-10 stream (pid, step0 + s),
+ * each word pair (w0, w1) read as the double ((w1 << 32 | w0) >> 11) * 2^-53
+ * in [0, 1):
+ *   v <- v - (gamma_over_m * v) * dt
+ *   v <- v + (2 r - 1) * sqrt(dt)
+ *   x <- x + v * dt
+ * for both components, every operation one IEEE float64 operation.
+ * d_x, d_y, d_vx, d_vy: device float64 arrays of n entries (SoA), read and
+ *   written in place; 8-byte aligned, not overlapping.
+ * steps_per_launch: steps run per kernel launch with the particle kept in
+ *   registers; 1 is the paper's one launch per step, 0 runs all steps in one
+ *   launch.  Results are identical for every value.
+ * Resuming from saved state with step0 = k continues the same run.
+ * Errors: EINVAL (NULL or misaligned array, dt negative or not finite,
+ *         gamma_over_m not finite), ERANGE (step0 + n_steps - 1 > 2^32 - 1, or
+ *         pid0 + n - 1 overflows 64 bits).  n = 0 or n_steps = 0 does nothing.
+ */
+int orng_bd2(uint64_t pid0, uint32_t n, uint32_t step0, uint32_t n_steps, double dt,
+             double gamma_over_m, double *d_x, double *d_y, double *d_vx, double *d_vy,
+             uint32_t steps_per_launch, void *stream);
+
+/*
  * orng_normal_pairs -- the library's Box-Muller transform applied to
  * caller-supplied 32-bit words: (z0[i], z1[i]) is the normal pair made from
  * (x0[i], x1[i]) exactly as F32_NORMAL samples 2m and 2m+1 are made from

@@ -1,0 +1,98 @@
+// The paper's 2-D Brownian dynamics example (section 4, Fig. 1; the GPU
+// benchmark of section 5.1): every particle is one stream, seeded by its id
+// and counted by the step, so a step needs no state besides the particle.
+//
+// Per particle and step (float64, every operation rounded once; the build
+// turns contraction off):
+//   r = two doubles from words 0..3 of Philox stream (pid, step0 + s)
+//   v <- v - (c v) dt        c = gamma / mass           (drag)
+//   v <- v + (2 r - 1) sqrt(dt)                         (uniform kick)
+//   x <- x + v dt                                       (move)
+// The paper launches one kernel per step and loads and stores the particle
+// each time; here a launch runs steps_per_launch steps with the particle in
+// registers (0: all steps in one launch).  Results are the same for every
+// value, since each step's randoms depend only on (pid, step).
+#include "../../include/orng.h"
+#include "orng_device.hpp"
+#include "orng_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace orng {
+
+struct Bd2Args {
+    double *x, *y, *vx, *vy;
+    uint64_t pid0;
+    uint32_t n, step0, n_steps, pad;
+    double dt, c, sqrt_dt;
+};
+
+// float64 in [0, 1) from the words at positions 2j (w0) and 2j+1 (w1): the top
+// 53 bits of (w1 << 32 | w0) times 2^-53.  w1 * 2^21 + (w0 >> 11) is an integer
+// below 2^53, so the fma is exact, and so is the power-of-two scaling.
+__device__ __forceinline__ double u01_f64(uint32_t w0, uint32_t w1) {
+    return fma((double)w1, 0x1p21, (double)(w0 >> 11)) * 0x1p-53;
+}
+
+__global__ __launch_bounds__(256) void k_bd2(Bd2Args a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const uint64_t pid = a.pid0 + i;
+    const uint32_t klo = (uint32_t)pid, khi = (uint32_t)(pid >> 32);
+    double px = a.x[i], py = a.y[i], ux = a.vx[i], uy = a.vy[i];
+    const double c = a.c, dt = a.dt, sq = a.sqrt_dt;
+    for (uint32_t s = 0; s < a.n_steps; ++s) {
+        uint32_t w[4];
+        philox_block0_lanekey(a.step0 + s, klo, khi, w);
+        const double rx = u01_f64(w[0], w[1]);
+        const double ry = u01_f64(w[2], w[3]);
+        ux = ux - c * ux * dt;
+        uy = uy - c * uy * dt;
+        ux = ux + (rx * 2.0 - 1.0) * sq;
+        uy = uy + (ry * 2.0 - 1.0) * sq;
+        px = px + ux * dt;
+        py = py + uy * dt;
+    }
+    a.x[i] = px;
+    a.y[i] = py;
+    a.vx[i] = ux;
+    a.vy[i] = uy;
+}
+
+}  // namespace orng
+
+using namespace orng;
+
+extern "C" int orng_bd2(uint64_t pid0, uint32_t n, uint32_t step0, uint32_t n_steps, double dt,
+                        double gamma_over_m, double *x, double *y, double *vx, double *vy,
+                        uint32_t steps_per_launch, void *stream) {
+    if (!std::isfinite(dt) || dt < 0.0 || !std::isfinite(gamma_over_m)) return ORNG_EINVAL;
+    if (n_steps && (uint64_t)step0 + n_steps - 1 > 0xFFFFFFFFull) return ORNG_ERANGE;
+    if (n && pid0 + (n - 1) < pid0) return ORNG_ERANGE;
+    if (!n || !n_steps) return ORNG_OK;
+    for (const double *p : {x, y, vx, vy})
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 7u)) return ORNG_EINVAL;
+    Bd2Args a;
+    a.x = x;
+    a.y = y;
+    a.vx = vx;
+    a.vy = vy;
+    a.pid0 = pid0;
+    a.n = n;
+    a.pad = 0;
+    a.dt = dt;
+    a.c = gamma_over_m;
+    a.sqrt_dt = std::sqrt(dt);
+    const uint32_t per = steps_per_launch ? steps_per_launch : n_steps;
+    const uint32_t grid = (n + 255) / 256;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (uint32_t done = 0; done < n_steps; done += std::min(per, n_steps - done)) {
+        a.step0 = step0 + done;
+        a.n_steps = std::min(per, n_steps - done);
+        hipLaunchKernelGGL(k_bd2, dim3(grid), dim3(256), 0, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; }
+    }
+    return ORNG_OK;
+}

@@ -62,6 +62,28 @@ __device__ __forceinline__ void philox_block(uint32_t c0, uint32_t c1, const Key
     o[0] = x0; o[1] = x1; o[2] = x2; o[3] = x3;
 }
 
+// Block 0 of Philox stream (seed, c1) with the key in VGPRs, for kernels in
+// which every lane has its own seed (one stream per particle): round r uses
+// (lo + r W0, hi + r W1), bumped as the rounds go.
+__device__ __forceinline__ void philox_block0_lanekey(uint32_t c1, uint32_t klo, uint32_t khi,
+                                                      uint32_t o[4]) {
+    uint32_t x0 = 0u, x1 = c1, x2 = 0u, x3 = 0u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)x0 * 0xD2511F53u;
+        const uint64_t b = (uint64_t)x2 * 0xCD9E8D57u;
+        const uint32_t n0 = xor3((uint32_t)(b >> 32), x1, klo);
+        const uint32_t n2 = xor3((uint32_t)(a >> 32), x3, khi);
+        x1 = (uint32_t)b;
+        x3 = (uint32_t)a;
+        x0 = n0;
+        x2 = n2;
+        klo += 0x9E3779B9u;
+        khi += 0xBB67AE85u;
+    }
+    o[0] = x0; o[1] = x1; o[2] = x2; o[3] = x3;
+}
+
 // ---------------------------------------------------------------------------
 // Threefry4x32-20.  Counter (c0, c1, 0, 0), key (lo seed, hi seed, 0, 0).
 // Mixing pairs follow the Threefish permutation: (0,1)(2,3) on even rounds,

@@ -30,6 +30,13 @@ BULK_N = 1 << 30
 # walk: 2^24 particles in 3-D, 10^4 steps, dt = 1e-3, D = 1, from the origin
 WALK = dict(n_particles=1 << 24, dim=3, n_steps=10_000, dt=1e-3, D=1.0, msd_every=1000)
 
+# The paper's own 2-D Brownian dynamics run (section 5.1): one million
+# particles, 10,000 steps, the generator of each particle keyed by its id and
+# the loop iteration (which starts at 1).  Drag coefficient and time step are
+# not given; gamma/mass = 1 and dt = 1e-3 here.  Particles start at rest at
+# the origin.
+BD2 = dict(n=1_000_000, pid0=0, step0=1, n_steps=10_000, dt=1e-3, gamma_over_m=1.0)
+
 
 def batched_requests(n: int = 100_000, seed: int = 3, max_log2: float = 20.0):
     """Uneven Philox streams: lengths log-uniform in [1, 2^max_log2] words,

@@ -70,6 +70,7 @@ def _load():
         "orng_fill": [i32, i32, u64, u32, u64, u64, vp, vp],
         "orng_fill_multi": [i32, i32, u64, u32, u32, u64, u64, vp, vp],
         "orng_brownian": [u64, u32, u32, u32, u64, u32, f32, f32, vp, vp, u32, vp],
+        "orng_bd2": [u64, u32, u32, u32, C.c_double, C.c_double, vp, vp, vp, vp, u32, vp],
         "orng_normal_pairs": [vp, vp, u64, vp, vp, vp],
         "orng_fill_batched": [vp, C.c_size_t, vp],
         "orng_fill_each": [vp, C.c_size_t, vp],
@@ -141,6 +142,12 @@ def orng_brownian(seed, ctr0, n_particles, dim, step0, n_steps, dt, D, pos, msd=
                   msd_every=0, stream=None):
     _check(_lib.orng_brownian(seed, ctr0, n_particles, dim, step0, n_steps, dt, D, _ptr(pos),
                               _ptr(msd), msd_every, _stream(stream)), "orng_brownian")
+
+
+def orng_bd2(pid0, n, step0, n_steps, dt, gamma_over_m, x, y, vx, vy, steps_per_launch=0,
+             stream=None):
+    _check(_lib.orng_bd2(pid0, n, step0, n_steps, dt, gamma_over_m, _ptr(x), _ptr(y), _ptr(vx),
+                         _ptr(vy), steps_per_launch, _stream(stream)), "orng_bd2")
 
 
 def orng_set_launch(wg_size=0, unroll=0, max_wgs=0, nontemporal=0):

@@ -22,6 +22,7 @@ def L():
     lib.orng_fill_multi.argtypes = [i32, i32, u64, u32, u32, u64, u64, vp, vp]
     lib.orng_brownian.argtypes = [u64, u32, u32, u32, u64, u32, f32, f32, vp, vp, u32, vp]
     lib.orng_normal_pairs.argtypes = [vp, vp, u64, vp, vp, vp]
+    lib.orng_bd2.argtypes = [u64, u32, u32, u32, C.c_double, C.c_double, vp, vp, vp, vp, u32, vp]
     lib.orng_fill_batched.argtypes = [vp, C.c_size_t, vp]
     lib.orng_fill_each.argtypes = [vp, C.c_size_t, vp]
     lib.orng_tune_load.argtypes = [C.c_char_p]
@@ -61,6 +62,20 @@ def test_brownian_validation(L):
     assert L.orng_brownian(1, 0, 4, 3, 0, 1, 1e-3, 1.0, None, None, 0, None) == EINVAL
     assert L.orng_brownian(1, 0, 4, 3, 0, 1, 1e-3, 1.0, FAKE, FAKE + 4, 1, None) == EINVAL
     assert L.orng_brownian(1, 0, 0, 3, 0, 1, 1e-3, 1.0, None, None, 0, None) == 0
+
+
+def test_bd2_validation(L):
+    F = (FAKE, FAKE + 64, FAKE + 128, FAKE + 192)
+    assert L.orng_bd2(1, 4, 2**32 - 1, 2, 1e-3, 1.0, *F, 0, None) == ERANGE
+    assert L.orng_bd2(2**64 - 2, 4, 1, 1, 1e-3, 1.0, *F, 0, None) == ERANGE
+    assert L.orng_bd2(1, 4, 1, 1, -1e-3, 1.0, *F, 0, None) == EINVAL
+    assert L.orng_bd2(1, 4, 1, 1, float("inf"), 1.0, *F, 0, None) == EINVAL
+    assert L.orng_bd2(1, 4, 1, 1, 1e-3, float("nan"), *F, 0, None) == EINVAL
+    assert L.orng_bd2(1, 4, 1, 1, 1e-3, 1.0, FAKE, None, FAKE, FAKE, 0, None) == EINVAL
+    assert L.orng_bd2(1, 4, 1, 1, 1e-3, 1.0, FAKE, FAKE + 4, FAKE, FAKE, 0, None) == EINVAL
+    # nothing to do: no pointer is looked at
+    assert L.orng_bd2(1, 0, 1, 5, 1e-3, 1.0, None, None, None, None, 0, None) == 0
+    assert L.orng_bd2(1, 4, 1, 0, 1e-3, 1.0, None, None, None, None, 0, None) == 0
 
 
 def test_normal_pairs_validation(L):
