@@ -72,14 +72,14 @@ def roofs(gen, dist, n, ms):
 # calibration factors a 1 GiB device copy gives for each counter.  Valid only
 # for the kernel sources and launch table they were measured on: bench.py
 # reports null traffic when the hash of those sources differs.
-TRAFFIC_SRC_SHA = "8ff78c0fcb673050"
-TRAFFIC_FACTORS = (1.9999225169637187, 1.0)  # FETCH, WRITE
+TRAFFIC_SRC_SHA = "d4bb6d7e71669f40"
+TRAFFIC_FACTORS = (1.999922278563641, 1.0)  # FETCH, WRITE
 TRAFFIC_KIB = {
-    (0, 0): (65.25, 4194349.875), (0, 1): (32.9375, 4195287.875), (0, 2): (80.3125, 4194314.0),
-    (1, 0): (55.0, 4194322.625), (1, 1): (33.5, 4194308.125), (1, 2): (43.0, 4194304.0),
-    (2, 0): (34.625, 4194304.0), (2, 1): (33.625, 4194327.0), (2, 2): (42.1875, 4194304.875),
-    (3, 0): (34.4375, 4194938.875), (3, 1): (35.0625, 4194323.875), (3, 2): (42.3125, 4194307.5),
-    (4, 0): (75.4375, 4194304.0), (4, 1): (29.0, 4194304.0), (4, 2): (36.5, 4194304.0),
+    (0, 0): (65.125, 4194304.0), (0, 1): (33.0, 4194451.75), (0, 2): (54.4375, 4194319.5),
+    (1, 0): (39.625, 4194304.0), (1, 1): (39.125, 4194323.875), (1, 2): (41.5, 4194304.25),
+    (2, 0): (33.5, 4194322.875), (2, 1): (35.625, 4194338.375), (2, 2): (40.0, 4194304.0),
+    (3, 0): (29.0, 4194304.0), (3, 1): (25.0, 4194405.75), (3, 2): (83.0625, 4194304.0),
+    (4, 0): (38.3125, 4194304.0), (4, 1): (26.9375, 4194304.0), (4, 2): (40.75, 4194398.625),
 }
 
 
