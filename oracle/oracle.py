@@ -18,9 +18,9 @@ SRC = os.path.join(HERE, "orng_oracle.cc")
 LIB = os.path.join(HERE, "liborng_oracle.so")
 
 PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE = range(5)
-U32, F32_UNIFORM, F32_NORMAL = range(3)
+U32, F32_UNIFORM, F32_NORMAL, F64_UNIFORM = range(4)
 GENS = (PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE)
-DISTS = (U32, F32_UNIFORM, F32_NORMAL)
+DISTS = (U32, F32_UNIFORM, F32_NORMAL)  # the float32/u32 set; F64_UNIFORM is separate
 
 # contraction off: each float operation in the source is one IEEE operation
 CXXFLAGS = ["-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
@@ -196,7 +196,7 @@ def normal_pair_n(x0, x1):
 
 
 def _dtype(dist):
-    return np.uint32 if dist == U32 else np.float32
+    return {U32: np.uint32, F64_UNIFORM: np.float64}.get(dist, np.float32)
 
 
 def fill(gen, dist, seed, ctr, offset, n, nthreads=None):

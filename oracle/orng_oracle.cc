@@ -191,6 +191,14 @@ void samples_range(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t p0, 
         for (uint64_t j = 0; j < count; ++j) o[j] = oracle_u01(w[j]);
         return;
     }
+    if (dist == OR_F64_UNIFORM) {
+        /* sample p is made from words 2p and 2p+1 */
+        std::vector<uint32_t> w(2 * count);
+        words_range(gen, seed, ctr, 2 * p0, 2 * count, w.data());
+        double *o = (double *)dst;
+        for (uint64_t j = 0; j < count; ++j) o[j] = oracle_u01_f64(w[2 * j], w[2 * j + 1]);
+        return;
+    }
     /* normal: sample p is member (p mod 2) of pair p/2, which is built from
        words 2*(p/2) and 2*(p/2)+1 */
     const uint64_t m0 = p0 / 2, m1 = (p0 + count - 1) / 2;
@@ -206,7 +214,10 @@ void samples_range(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t p0, 
 }
 
 bool valid_gen(int g) { return g >= OR_PHILOX && g <= OR_TYCHE; }
-bool valid_dist(int d) { return d >= OR_U32 && d <= OR_F32_NORMAL; }
+bool valid_dist(int d) { return d >= OR_U32 && d <= OR_F64_UNIFORM; }
+/* bytes per sample, and stream positions (words) per sample */
+uint64_t sample_bytes(int dist) { return dist == OR_F64_UNIFORM ? 8 : 4; }
+uint64_t sample_limit(int dist) { return dist == OR_F64_UNIFORM ? (1ull << 31) : (1ull << 32); }
 
 template <class F>
 void parallel_ranges(uint64_t n, int nthreads, F body) {
@@ -340,6 +351,12 @@ void oracle_sample(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t p, v
         /* use the direct per-word form so a single sample costs O(256) MIX */
         if (dist == OR_U32) { uint32_t w = oracle_word(gen, seed, ctr, p); std::memcpy(out, &w, 4); return; }
         if (dist == OR_F32_UNIFORM) { float f = oracle_u01(oracle_word(gen, seed, ctr, p)); std::memcpy(out, &f, 4); return; }
+        if (dist == OR_F64_UNIFORM) {
+            const double d = oracle_u01_f64(oracle_word(gen, seed, ctr, 2 * p),
+                                            oracle_word(gen, seed, ctr, 2 * p + 1));
+            std::memcpy(out, &d, 8);
+            return;
+        }
         uint64_t m = p / 2;
         float pair[2];
         oracle_normal_pair(oracle_word(gen, seed, ctr, 2 * m), oracle_word(gen, seed, ctr, 2 * m + 1), pair);
@@ -476,12 +493,13 @@ void oracle_normal_pair_n(const uint32_t *x0, const uint32_t *x1, uint64_t n, fl
 int oracle_fill(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t offset, uint64_t n,
                 void *out, int nthreads) {
     if (!valid_gen(gen) || !valid_dist(dist)) return -1;
-    if (offset > PERIOD || n > PERIOD - offset) return -2;
+    const uint64_t lim = sample_limit(dist), sb = sample_bytes(dist);
+    if (offset > lim || n > lim - offset) return -2;
     char *o = (char *)out;
     parallel_ranges(n, nthreads, [&](uint64_t a, uint64_t b, int) {
         for (uint64_t j = a; j < b; j += PIECE) {
             uint64_t c = (b - j < PIECE) ? b - j : PIECE;
-            samples_range(gen, dist, seed, ctr, offset + j, c, o + 4 * j);
+            samples_range(gen, dist, seed, ctr, offset + j, c, o + sb * j);
         }
     });
     return 0;
@@ -490,13 +508,14 @@ int oracle_fill(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t offset,
 int oracle_fill_multi(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t n_streams,
                       uint64_t offset, uint64_t per_stream, void *out, int nthreads) {
     if (!valid_gen(gen) || !valid_dist(dist)) return -1;
-    if (offset > PERIOD || per_stream > PERIOD - offset) return -2;
+    const uint64_t lim = sample_limit(dist), sb = sample_bytes(dist);
+    if (offset > lim || per_stream > lim - offset) return -2;
     if (n_streams && (uint64_t)ctr0 + n_streams - 1 > 0xFFFFFFFFull) return -2;
     char *o = (char *)out;
     parallel_ranges(n_streams, nthreads, [&](uint64_t a, uint64_t b, int) {
         for (uint64_t i = a; i < b; ++i)
             samples_range(gen, dist, seed, ctr0 + (uint32_t)i, offset, per_stream,
-                          o + 4 * i * per_stream);
+                          o + sb * i * per_stream);
     });
     return 0;
 }
@@ -505,7 +524,8 @@ void oracle_samples_at(int gen, int dist, uint64_t seed, const uint32_t *ctrs,
                        const uint64_t *pos, uint64_t count, void *out, int nthreads) {
     char *o = (char *)out;
     parallel_ranges(count, nthreads, [&](uint64_t a, uint64_t b, int) {
-        for (uint64_t k = a; k < b; ++k) oracle_sample(gen, dist, seed, ctrs[k], pos[k], o + 4 * k);
+        for (uint64_t k = a; k < b; ++k)
+            oracle_sample(gen, dist, seed, ctrs[k], pos[k], o + sample_bytes(dist) * k);
     });
 }
 

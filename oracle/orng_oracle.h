@@ -41,7 +41,7 @@ extern "C" {
 /* generator and distribution codes (same numbering as the public API; the
    numbers are part of the interface, not shared code) */
 enum { OR_PHILOX = 0, OR_THREEFRY4X32 = 1, OR_THREEFRY2X64 = 2, OR_SQUARES = 3, OR_TYCHE = 4 };
-enum { OR_U32 = 0, OR_F32_UNIFORM = 1, OR_F32_NORMAL = 2 };
+enum { OR_U32 = 0, OR_F32_UNIFORM = 1, OR_F32_NORMAL = 2, OR_F64_UNIFORM = 3 };
 
 /* --- raw generator cores ------------------------------------------------ */
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -56,7 +56,9 @@ uint32_t oracle_tyche_next(uint32_t st[4]);        /* one MIX, returns b */
 /* --- stream model -------------------------------------------------------- */
 /* word at position p of stream (seed, ctr) of generator gen */
 uint32_t oracle_word(int gen, uint64_t seed, uint32_t ctr, uint64_t p);
-/* sample at position p of the given distribution; writes 4 bytes to *out */
+/* sample at position p of the given distribution; writes 4 bytes to *out
+   (8 for OR_F64_UNIFORM, whose sample p is made from words 2p and 2p+1, so
+   its positions end at 2^31) */
 void oracle_sample(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t p, void *out);
 
 /* --- float32 conversions --------------------------------------------------- */
