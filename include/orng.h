@@ -45,11 +45,12 @@ enum {
     ORNG_TYCHE = 4
 };
 
-/* distributions; every sample is 4 bytes */
+/* distributions; samples are 4 bytes, 8 for ORNG_F64_UNIFORM */
 enum {
-    ORNG_U32 = 0,        /* raw 32-bit word */
+    ORNG_U32 = 0,         /* raw 32-bit word */
     ORNG_F32_UNIFORM = 1, /* (word >> 8) * 2^-24, in [0, 1) */
-    ORNG_F32_NORMAL = 2  /* Box-Muller, one member of a pair per sample */
+    ORNG_F32_NORMAL = 2,  /* Box-Muller, one member of a pair per sample */
+    ORNG_F64_UNIFORM = 3  /* two words per sample: ((w1 << 32 | w0) >> 11) * 2^-53, in [0, 1) */
 };
 
 /* status codes */
@@ -68,7 +69,9 @@ enum {
  * orng_fill -- out[j] = sample (offset + j) of stream (seed, ctr), j < n.
  *
  * Paper section 3.1 (stream = seed + counter, period 2^32).  Sample p of a
- * distribution uses word p (U32, F32_UNIFORM); for F32_NORMAL, sample p is
+ * distribution uses word p (U32, F32_UNIFORM); F64_UNIFORM sample p uses
+ * words 2p (w0) and 2p+1 (w1), so its samples end at 2^31 (the float64 draw
+ * of the paper's example, section 4 Fig. 1); for F32_NORMAL, sample p is
  * member p mod 2 of the Box-Muller pair built from words 2*(p/2) and
  * 2*(p/2)+1.  The stream's words are:
  *   Philox4x32-10  : word p = word p%4 of Philox(counter (p/4, ctr, 0, 0),
@@ -82,8 +85,10 @@ enum {
  *                    r = p % 16384 is output 4*(r/256) + r%4 of the Tyche
  *                    instance seeded with (seed, ctr) whose c word is XORed
  *                    with t*64 + (r/4)%64.
- * Arguments: gen, dist (enums above); d_out: device buffer of n * 4 bytes.
- * Errors: EINVAL (enum, NULL, alignment), ERANGE (offset + n > 2^32).
+ * Arguments: gen, dist (enums above); d_out: device buffer of n samples
+ * (n * 4 bytes, 4-byte aligned; n * 8 bytes, 8-byte aligned for F64_UNIFORM).
+ * Errors: EINVAL (enum, NULL, alignment), ERANGE (offset + n past the last
+ *         sample: 2^32, or 2^31 for F64_UNIFORM).
  */
 int orng_fill(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t offset, uint64_t n,
               void *d_out, void *stream);

@@ -39,7 +39,7 @@ static int hip_status(hipError_t e) {
 }
 
 static bool valid_gen(int g) { return g >= ORNG_PHILOX4X32_10 && g <= ORNG_TYCHE; }
-static bool valid_dist(int d) { return d >= ORNG_U32 && d <= ORNG_F32_NORMAL; }
+static bool valid_dist(int d) { return d >= ORNG_U32 && d <= ORNG_F64_UNIFORM; }
 
 }  // namespace orng
 
@@ -50,22 +50,24 @@ extern "C" {
 int orng_fill(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t offset, uint64_t n,
               void *d_out, void *stream) {
     if (!valid_gen(gen) || !valid_dist(dist)) return ORNG_EINVAL;
-    if (offset > PERIOD || n > PERIOD - offset) return ORNG_ERANGE;
+    const uint64_t k = words_per_sample(dist), lim = sample_limit(dist);
+    if (offset > lim || n > lim - offset) return ORNG_ERANGE;
     if (n == 0) return ORNG_OK;
-    if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 3u)) return ORNG_EINVAL;
-    return hip_status(launch_fill(gen, dist, seed, ctr, 1, offset, n, d_out,
+    if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & (4 * k - 1))) return ORNG_EINVAL;
+    return hip_status(launch_fill(gen, dist, seed, ctr, 1, offset * k, n * k, d_out,
                                   static_cast<hipStream_t>(stream)));
 }
 
 int orng_fill_multi(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t n_streams,
                     uint64_t offset, uint64_t per_stream, void *d_out, void *stream) {
     if (!valid_gen(gen) || !valid_dist(dist)) return ORNG_EINVAL;
-    if (offset > PERIOD || per_stream > PERIOD - offset) return ORNG_ERANGE;
+    const uint64_t k = words_per_sample(dist), lim = sample_limit(dist);
+    if (offset > lim || per_stream > lim - offset) return ORNG_ERANGE;
     if (n_streams && (uint64_t)ctr0 + n_streams - 1 > 0xFFFFFFFFull) return ORNG_ERANGE;
     if (n_streams == 0 || per_stream == 0) return ORNG_OK;
-    if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 3u)) return ORNG_EINVAL;
-    return hip_status(launch_fill(gen, dist, seed, ctr0, n_streams, offset, per_stream, d_out,
-                                  static_cast<hipStream_t>(stream)));
+    if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & (4 * k - 1))) return ORNG_EINVAL;
+    return hip_status(launch_fill(gen, dist, seed, ctr0, n_streams, offset * k, per_stream * k,
+                                  d_out, static_cast<hipStream_t>(stream)));
 }
 
 int orng_brownian(uint64_t seed, uint32_t ctr0, uint32_t n_particles, uint32_t dim,

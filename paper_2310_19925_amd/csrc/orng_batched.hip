@@ -218,10 +218,11 @@ static void *batched_kernel(const BatchShape &s) {
 }
 
 int validate_request(const orng_req_t &r) {
-    if (r.gen > ORNG_TYCHE || r.dist > ORNG_F32_NORMAL || r.flags != 0) return ORNG_EINVAL;
-    if (r.offset > PERIOD || r.n > PERIOD - r.offset) return ORNG_ERANGE;
+    if (r.gen > ORNG_TYCHE || r.dist > ORNG_F64_UNIFORM || r.flags != 0) return ORNG_EINVAL;
+    const uint64_t k = words_per_sample((int)r.dist), lim = sample_limit((int)r.dist);
+    if (r.offset > lim || r.n > lim - r.offset) return ORNG_ERANGE;
     if (r.n == 0) return ORNG_OK;
-    if (!r.out || (reinterpret_cast<uintptr_t>(r.out) & 3u)) return ORNG_EINVAL;
+    if (!r.out || (reinterpret_cast<uintptr_t>(r.out) & (4 * k - 1))) return ORNG_EINVAL;
     return ORNG_OK;
 }
 
@@ -230,7 +231,8 @@ int validate_request(const orng_req_t &r) {
 void request_tiles(const orng_req_t &r, uint32_t unroll, uint32_t W, uint64_t *first_span,
                    uint64_t *count) {
     const uint64_t sb = span_blocks((int)r.gen, unroll);
-    const uint64_t fb = r.offset / 4, lb = (r.offset + r.n - 1) / 4;
+    const uint64_t k = words_per_sample((int)r.dist);
+    const uint64_t fb = r.offset * k / 4, lb = ((r.offset + r.n) * k - 1) / 4;
     *first_span = fb / sb;
     const uint64_t spans = lb / sb - *first_span + 1;
     *count = (spans + W - 1) / W;
@@ -260,9 +262,10 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     std::vector<uint32_t> unr(live.size());
     const orng_req_t &r0 = reqs[live[0]];
     const uint32_t W = batch_wg((int)r0.gen, (int)r0.dist) / 64;
-    uint32_t unroll_of[5][3];  // one table lookup per pair, not per request
-    for (int g = 0; g < 5; ++g)
-        for (int d = 0; d < 3; ++d) unroll_of[g][d] = g == G_TYCHE ? 64 : tuned_fill(g, d).b_unroll;
+    uint32_t unroll_of[NGEN][NDIST];  // one table lookup per pair, not per request
+    for (int g = 0; g < NGEN; ++g)
+        for (int d = 0; d < NDIST; ++d)
+            unroll_of[g][d] = g == G_TYCHE ? 64 : tuned_fill(g, d).b_unroll;
     uint64_t tiles = 0;
     for (size_t k = 0; k < live.size(); ++k) {
         const orng_req_t &r = reqs[live[k]];
@@ -301,16 +304,17 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     for (size_t k = 0; k < live.size(); ++k) {
         const orng_req_t &r = reqs[live[k]];
         DevReq &d = dq[k];
+        const uint64_t kw = words_per_sample((int)r.dist);
         d.out = static_cast<char *>(r.out);
-        d.p0 = r.offset;
-        d.n = r.n;
+        d.p0 = r.offset * kw;  // positions and counts in stream words from here on
+        d.n = r.n * kw;
         d.seed = r.seed;
         d.first_span = fspan[k];
         d.tile_start = ts;
         d.ctr = r.ctr;
         d.unroll = unr[k];
         const uint64_t addr_words = reinterpret_cast<uintptr_t>(r.out) / 4;
-        const uint32_t delta = (uint32_t)((addr_words - r.offset) & 3u);
+        const uint32_t delta = (uint32_t)((addr_words - d.p0) & 3u);
         d.flags = r.gen | (r.dist << 4) | (delta << 8);
         d.pad = 0;
         std::fill_n(map + ts, cnt[k], (uint32_t)k);
@@ -368,8 +372,9 @@ int orng_fill_each(const orng_req_t *h_reqs, size_t nreq, void *stream) {
     for (size_t i = 0; i < nreq; ++i) {
         const orng_req_t &r = h_reqs[i];
         if (!r.n) continue;
-        hipError_t e = orng::launch_fill((int)r.gen, (int)r.dist, r.seed, r.ctr, 1, r.offset, r.n,
-                                         r.out, static_cast<hipStream_t>(stream));
+        const uint64_t k = orng::words_per_sample((int)r.dist);
+        hipError_t e = orng::launch_fill((int)r.gen, (int)r.dist, r.seed, r.ctr, 1, r.offset * k,
+                                         r.n * k, r.out, static_cast<hipStream_t>(stream));
         if (e != hipSuccess) {
             orng::set_hip_error(e);
             return ORNG_EHIP;

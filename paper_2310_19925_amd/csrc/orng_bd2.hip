@@ -28,13 +28,6 @@ struct Bd2Args {
     double dt, c, sqrt_dt;
 };
 
-// float64 in [0, 1) from the words at positions 2j (w0) and 2j+1 (w1): the top
-// 53 bits of (w1 << 32 | w0) times 2^-53.  w1 * 2^21 + (w0 >> 11) is an integer
-// below 2^53, so the fma is exact, and so is the power-of-two scaling.
-__device__ __forceinline__ double u01_f64(uint32_t w0, uint32_t w1) {
-    return fma((double)w1, 0x1p21, (double)(w0 >> 11)) * 0x1p-53;
-}
-
 __global__ __launch_bounds__(256) void k_bd2(Bd2Args a) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;

@@ -23,7 +23,8 @@
 namespace orng {
 
 enum GenId : int { G_PHILOX = 0, G_TF4X32 = 1, G_TF2X64 = 2, G_SQUARES = 3, G_TYCHE = 4 };
-enum DistId : int { D_U32 = 0, D_UNIFORM = 1, D_NORMAL = 2 };
+enum DistId : int { D_U32 = 0, D_UNIFORM = 1, D_NORMAL = 2, D_F64U = 3 };
+constexpr int NGEN = 5, NDIST = 4;
 
 // Per-launch key material, uniform across the grid.
 struct KeySched {
@@ -387,7 +388,16 @@ __device__ __forceinline__ void normal_pair(uint32_t x0, uint32_t x1, float &z0,
     z1 = r * s;
 }
 
-// Convert a block of four words to four output samples (bit patterns).
+// float64 in [0, 1) from the words at positions 2j (w0) and 2j+1 (w1): the top
+// 53 bits of (w1 << 32 | w0) times 2^-53.  w1 * 2^21 + (w0 >> 11) is an integer
+// below 2^53, so the fma is exact, and so is the power-of-two scaling.
+__device__ __forceinline__ double u01_f64(uint32_t w0, uint32_t w1) {
+    return fma((double)w1, 0x1p21, (double)(w0 >> 11)) * 0x1p-53;
+}
+
+// Convert a block of four words to the output words of its samples (bit
+// patterns): four float32/u32 samples, or two float64 samples (little-endian
+// word order) for D_F64U.
 template <int D>
 __device__ __forceinline__ void convert4(uint32_t w[4]) {
     if constexpr (D == D_UNIFORM) {
@@ -399,6 +409,11 @@ __device__ __forceinline__ void convert4(uint32_t w[4]) {
         normal_pair(w[2], w[3], c, d);
         w[0] = __float_as_uint(a); w[1] = __float_as_uint(b);
         w[2] = __float_as_uint(c); w[3] = __float_as_uint(d);
+    } else if constexpr (D == D_F64U) {
+        const uint64_t a = (uint64_t)__double_as_longlong(u01_f64(w[0], w[1]));
+        const uint64_t b = (uint64_t)__double_as_longlong(u01_f64(w[2], w[3]));
+        w[0] = (uint32_t)a; w[1] = (uint32_t)(a >> 32);
+        w[2] = (uint32_t)b; w[3] = (uint32_t)(b >> 32);
     }
 }
 

@@ -12,6 +12,13 @@ namespace orng {
 
 constexpr uint64_t PERIOD = 1ull << 32;
 
+// Stream words per sample: a float64 uniform sample is made from the word
+// pair (2p, 2p+1), every other distribution from one word.  The public calls
+// take offsets and counts in samples and convert them to words (positions)
+// once; below that, every launcher and kernel works in words.
+inline uint64_t words_per_sample(int dist) { return dist == D_F64U ? 2 : 1; }
+inline uint64_t sample_limit(int dist) { return PERIOD / words_per_sample(dist); }
+
 // Launch knobs.  0 means "choose automatically".
 struct LaunchCfg {
     uint32_t wg_size;   // threads per workgroup (multiple of 64, <= 512)
@@ -44,7 +51,8 @@ void set_launch_cfg(const LaunchCfg &c);
 void set_hip_error(hipError_t e);
 int last_hip_error();
 
-// Launchers; arguments already validated.  Return hipError_t.
+// Launchers; arguments already validated.  Return hipError_t.  launch_fill
+// takes offset and per_stream in stream words (positions).
 hipError_t launch_fill(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t n_streams,
                        uint64_t offset, uint64_t per_stream, void *out, hipStream_t s);
 hipError_t launch_walk(uint64_t seed, uint32_t ctr0, uint32_t n, uint32_t dim, uint64_t step0,

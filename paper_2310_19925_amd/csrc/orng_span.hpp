@@ -173,15 +173,15 @@ __device__ __forceinline__ void process_span_any(int gen, int dist, const KeySch
                                                  uint64_t pend, uint64_t span, uint32_t unroll,
                                                  uint32_t delta, uint32_t lane) {
 #define ORNG_CASE(G, D)                                                                    \
-    case G * 3 + D:                                                                        \
+    case G * NDIST + D:                                                                    \
         process_span<G, D, NT>(ks, ctr, base, p0, pend, span, unroll, delta, lane);        \
         break;
-    switch (gen * 3 + dist) {
-        ORNG_CASE(0, 0) ORNG_CASE(0, 1) ORNG_CASE(0, 2)
-        ORNG_CASE(1, 0) ORNG_CASE(1, 1) ORNG_CASE(1, 2)
-        ORNG_CASE(2, 0) ORNG_CASE(2, 1) ORNG_CASE(2, 2)
-        ORNG_CASE(3, 0) ORNG_CASE(3, 1) ORNG_CASE(3, 2)
-        ORNG_CASE(4, 0) ORNG_CASE(4, 1) ORNG_CASE(4, 2)
+    switch (gen * NDIST + dist) {
+        ORNG_CASE(0, 0) ORNG_CASE(0, 1) ORNG_CASE(0, 2) ORNG_CASE(0, 3)
+        ORNG_CASE(1, 0) ORNG_CASE(1, 1) ORNG_CASE(1, 2) ORNG_CASE(1, 3)
+        ORNG_CASE(2, 0) ORNG_CASE(2, 1) ORNG_CASE(2, 2) ORNG_CASE(2, 3)
+        ORNG_CASE(3, 0) ORNG_CASE(3, 1) ORNG_CASE(3, 2) ORNG_CASE(3, 3)
+        ORNG_CASE(4, 0) ORNG_CASE(4, 1) ORNG_CASE(4, 2) ORNG_CASE(4, 3)
         default: break;
     }
 #undef ORNG_CASE

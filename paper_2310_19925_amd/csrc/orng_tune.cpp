@@ -26,32 +26,37 @@ namespace orng {
 int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream);
 
 static std::mutex g_tune_mu;
-static Tuned g_tuned[5][3];
+static Tuned g_tuned[NGEN][NDIST];
 static bool g_tuned_init = false;
 
 // Measured on MI355X by orng_autotune (one entry per gen x dist, in
-// enum order): wg unroll max_wgs nontemporal | batched wg unroll chunk wgs/CU
+// enum order: u32, f32 uniform, f32 normal, f64 uniform): wg unroll max_wgs nontemporal | batched wg unroll chunk wgs/CU
 // (wgs/CU 0 = static one-workgroup-per-tile schedule).
-static const uint32_t kDefaultTable[15][8] = {
+static const uint32_t kDefaultTable[NGEN * NDIST][8] = {
         {64, 4, 0, 2, 512, 8, 1, 0},
         {64, 4, 0, 1, 512, 8, 1, 0},
         {512, 2, 8192, 1, 128, 16, 1, 0},
+        {64, 4, 0, 2, 512, 8, 1, 0},  // f64 uniform: the u32 shape until measured
         {512, 8, 8192, 2, 128, 16, 1, 0},
         {512, 8, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 1, 128, 16, 1, 0},
+        {512, 8, 8192, 2, 128, 16, 1, 0},  // f64 uniform: the u32 shape until measured
         {512, 4, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 1, 128, 16, 1, 0},
         {512, 4, 8192, 2, 128, 16, 1, 0},
+        {512, 4, 8192, 1, 128, 16, 1, 0},  // f64 uniform: the u32 shape until measured
         {64, 4, 0, 1, 256, 8, 1, 0},
         {64, 8, 0, 1, 256, 8, 1, 0},
         {256, 2, 8192, 1, 128, 16, 1, 0},
+        {64, 4, 0, 1, 256, 8, 1, 0},  // f64 uniform: the u32 shape until measured
         {64, 64, 0, 2, 512, 1, 1, 0},
         {64, 64, 0, 2, 512, 1, 1, 0},
         {256, 64, 0, 1, 128, 1, 1, 0},
+        {64, 64, 0, 2, 512, 1, 1, 0},  // f64 uniform: the u32 shape until measured
 };
 
 static Tuned default_tuned(int gen, int dist) {
-    const uint32_t *v = kDefaultTable[gen * 3 + dist];
+    const uint32_t *v = kDefaultTable[gen * NDIST + dist];
     Tuned t;
     t.wg_size = v[0];
     t.unroll = v[1];
@@ -66,8 +71,8 @@ static Tuned default_tuned(int gen, int dist) {
 
 static void init_locked() {
     if (g_tuned_init) return;
-    for (int g = 0; g < 5; ++g)
-        for (int d = 0; d < 3; ++d) g_tuned[g][d] = default_tuned(g, d);
+    for (int g = 0; g < NGEN; ++g)
+        for (int d = 0; d < NDIST; ++d) g_tuned[g][d] = default_tuned(g, d);
     g_tuned_init = true;
 }
 
@@ -115,7 +120,7 @@ static int load_locked(const char *path) {
         if (sscanf(line, "%d %d %u %u %u %u %u %u %u %u", &g, &d, &t.wg_size, &t.unroll,
                    &t.max_wgs, &t.nontemporal, &t.b_wg_size, &t.b_unroll, &t.b_chunk,
                    &t.b_wgs_per_cu) == 10 &&
-            g >= 0 && g < 5 && d >= 0 && d < 3 && sane(t, g)) {
+            g >= 0 && g < NGEN && d >= 0 && d < NDIST && sane(t, g)) {
             g_tuned[g][d] = t;
             ++loaded;
         }
@@ -138,8 +143,8 @@ int save_tune_cache(const char *path) {
     if (!f) return ORNG_EINVAL;
     fprintf(f, "# orng launch table: gen dist wg unroll max_wgs nontemporal "
                "batched_wg batched_unroll batched_chunk batched_wgs_per_cu\n");
-    for (int g = 0; g < 5; ++g)
-        for (int d = 0; d < 3; ++d) {
+    for (int g = 0; g < NGEN; ++g)
+        for (int d = 0; d < NDIST; ++d) {
             const Tuned &t = g_tuned[g][d];
             fprintf(f, "%d %d %u %u %u %u %u %u %u %u\n", g, d, t.wg_size, t.unroll, t.max_wgs,
                     t.nontemporal, t.b_wg_size, t.b_unroll, t.b_chunk, t.b_wgs_per_cu);
@@ -215,7 +220,7 @@ int orng_tune_load(const char *cache_path) {
 }
 
 int orng_autotune(int gen, int dist, const char *cache_path) {
-    if (gen < 0 || gen > 4 || dist < 0 || dist > 2) return ORNG_EINVAL;
+    if (gen < 0 || gen >= NGEN || dist < 0 || dist >= NDIST) return ORNG_EINVAL;
     const uint64_t n = 1ull << 30;  // 4 GiB of samples: the size of a bulk fill
     void *buf = nullptr;
     hipStream_t s = nullptr;
@@ -255,26 +260,28 @@ int orng_autotune(int gen, int dist, const char *cache_path) {
                       &e);
     set_tuned(gen, dist, best);
 
-    // batched: uneven requests packed back to back
+    // batched: uneven requests packed back to back (lengths in samples; a
+    // float64 sample takes two words of the buffer)
     std::mt19937_64 rng(12345);
     std::vector<orng_req_t> reqs;
-    uint64_t used = 0;
+    const uint64_t kw = words_per_sample(dist), lim = sample_limit(dist);
+    uint64_t used = 0;  // words
     while (reqs.size() < 8192) {
         const double u = std::uniform_real_distribution<double>(0.0, 20.0)(rng);
         uint64_t len = (uint64_t)std::pow(2.0, u);
         if (len < 1) len = 1;
-        if (used + len > n) break;
+        if (used + len * kw > n) break;
         orng_req_t r;
         r.seed = rng();
         r.ctr = (uint32_t)rng();
-        r.offset = rng() % (PERIOD - len + 1);
+        r.offset = rng() % (lim - len + 1);
         r.n = len;
         r.out = static_cast<char *>(buf) + used * 4;
         r.gen = (uint32_t)gen;
         r.dist = (uint32_t)dist;
         r.flags = 0;
         reqs.push_back(r);
-        used += len;
+        used += len * kw;
     }
     std::vector<std::pair<float, Tuned>> bc;
     bc.push_back({0.0f, best});  // the entry in use

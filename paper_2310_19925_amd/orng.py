@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborng.so")
 
 PHILOX4X32_10, THREEFRY4X32_20, THREEFRY2X64_20, SQUARES32, TYCHE = range(5)
-U32, F32_UNIFORM, F32_NORMAL = range(3)
+U32, F32_UNIFORM, F32_NORMAL, F64_UNIFORM = range(4)
 OK, EINVAL, ERANGE, ENOMEM, EAGAIN, EBUSY, EHIP, ENOENT = 0, -1, -2, -3, -4, -5, -6, -7
 
 
@@ -292,10 +292,16 @@ def orng_serve_destroy(srv):
 
 
 # -------- convenience wrappers that allocate the output tensor ---------------
-def fill(gen, dist, seed, ctr, offset, n, device="cuda", stream=None):
-    """Returns a new device tensor (uint32 viewed as int32 for U32, float32 otherwise)."""
+def _torch_dtype(dist):
     import torch
-    dt = torch.int32 if dist == U32 else torch.float32
+    return {U32: torch.int32, F64_UNIFORM: torch.float64}.get(dist, torch.float32)
+
+
+def fill(gen, dist, seed, ctr, offset, n, device="cuda", stream=None):
+    """Returns a new device tensor (uint32 viewed as int32 for U32, float64 for
+    F64_UNIFORM, float32 otherwise)."""
+    import torch
+    dt = _torch_dtype(dist)
     out = torch.empty(n, dtype=dt, device=device)
     orng_fill(gen, dist, seed, ctr, offset, n, out, stream)
     return out
@@ -303,7 +309,7 @@ def fill(gen, dist, seed, ctr, offset, n, device="cuda", stream=None):
 
 def fill_multi(gen, dist, seed, ctr0, n_streams, offset, per_stream, device="cuda", stream=None):
     import torch
-    dt = torch.int32 if dist == U32 else torch.float32
+    dt = _torch_dtype(dist)
     out = torch.empty(n_streams * per_stream, dtype=dt, device=device)
     orng_fill_multi(gen, dist, seed, ctr0, n_streams, offset, per_stream, out, stream)
     return out

@@ -159,10 +159,16 @@ def test_autotune_writes_cache_and_keeps_results(R, O, tmp_path):
     path = str(tmp_path / "tune.txt")
     R.orng_autotune(0, 1, path)
     text = open(path).read()
-    assert text.startswith("#") and len(text.strip().split("\n")) == 16
+    assert text.startswith("#") and len(text.strip().split("\n")) == 1 + 5 * 4
     R.orng_tune_load(path)
     rng = np.random.default_rng(6)
     _run_and_check(R, O, *_random_batch(rng, 100, gens=[0], dists=[1]))
     out = R.fill(0, 1, 9, 9, 3, 100003)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint32), O.fill(0, 1, 9, 9, 3, 100003).view(np.uint32))
+    # the float64 entry tunes with requests counted in doubles
+    R.orng_autotune(0, 3, path)
+    R.orng_tune_load(path)
+    out = R.fill(0, 3, 9, 9, 3, 100003)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.int64), O.fill(0, 3, 9, 9, 3, 100003).view(np.int64))

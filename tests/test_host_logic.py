@@ -36,7 +36,12 @@ FAKE = 0x10000  # a non-null, 16-byte aligned address that is never dereferenced
 
 def test_fill_validation(L):
     assert L.orng_fill(-1, 0, 1, 1, 0, 4, FAKE, None) == EINVAL
-    assert L.orng_fill(0, 3, 1, 1, 0, 4, FAKE, None) == EINVAL
+    assert L.orng_fill(0, 4, 1, 1, 0, 4, FAKE, None) == EINVAL
+    # float64 uniform: samples end at 2^31, 8-byte alignment
+    assert L.orng_fill(0, 3, 1, 1, 2**31 - 3, 4, FAKE, None) == ERANGE
+    assert L.orng_fill(0, 3, 1, 1, 2**31 + 1, 0, FAKE, None) == ERANGE
+    assert L.orng_fill(0, 3, 1, 1, 0, 4, FAKE + 4, None) == EINVAL
+    assert L.orng_fill(0, 3, 1, 1, 2**31, 0, None, None) == 0
     assert L.orng_fill(0, 0, 1, 1, 2**32 - 3, 4, FAKE, None) == ERANGE
     assert L.orng_fill(0, 0, 1, 1, 2**32 + 1, 0, FAKE, None) == ERANGE
     assert L.orng_fill(0, 0, 1, 1, 0, 4, FAKE + 2, None) == EINVAL
@@ -50,6 +55,8 @@ def test_fill_multi_validation(L):
     assert L.orng_fill_multi(0, 0, 1, 0, 0, 0, 4, None, None) == 0
     assert L.orng_fill_multi(0, 0, 1, 0, 5, 0, 0, None, None) == 0
     assert L.orng_fill_multi(7, 0, 1, 0, 5, 0, 4, FAKE, None) == EINVAL
+    assert L.orng_fill_multi(0, 3, 1, 0, 2, 2**31 - 1, 2, FAKE, None) == ERANGE
+    assert L.orng_fill_multi(0, 3, 1, 0, 2, 0, 2, FAKE + 4, None) == EINVAL
 
 
 def test_brownian_validation(L):
@@ -103,6 +110,8 @@ def test_batched_validation_rejects_whole_batch(L, fn):
         ([(0, 0, 2**32 - 8, 16, FAKE, 0)], ERANGE),                      # past the period
         ([(0, 0, 0, 16, 0, 0)], EINVAL),                                 # NULL output
         ([(0, 0, 0, 16, FAKE + 2, 0)], EINVAL),                          # misaligned output
+        ([(0, 3, 2**31 - 8, 16, FAKE, 0)], ERANGE),                      # float64 past 2^31
+        ([(0, 3, 0, 16, FAKE + 4, 0)], EINVAL),                          # float64, 4-byte aligned
     ]
     for rows, want in cases:
         r = _reqs(rows)
