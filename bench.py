@@ -53,14 +53,21 @@ VALU_PEAK_TSLOTS = 256 * 64 * 2.4e9 / 1e12
 #   f32 normal, per pair: 16 integer ops, 37 fp32 ops, rcp + rsq = 36.5 slots
 SLOTS_GEN = {0: 38 / 4, 1: 128 / 4, 2: 109 / 4, 3: 13 + 3 / 4, 4: 12 + 20 * 12 / 256}
 SLOTS_DIST = {0: 0.0, 1: 2.0, 2: 36.5 / 2}
+# float64 uniform: two words per sample, then shift, two conversions, one
+# exact fma and one scaling (float64 operations: one slot each at the
+# published 78.6 TFLOP/s vector rate); 8 bytes written per sample
+SLOTS_F64_CONVERT = 5
 
 
 def roofs(gen, dist, n, ms):
     """HBM and VALU roofline fractions of one fill launch; the binding roof is
     the one whose model time is longer."""
     t = ms * 1e-3
-    slots = (SLOTS_GEN[gen] + SLOTS_DIST[dist]) * n
-    t_hbm = 4.0 * n / (HBM_PEAK_GBS * 1e9)
+    if dist == 3:  # float64 uniform
+        slots, nbytes = (2 * SLOTS_GEN[gen] + SLOTS_F64_CONVERT) * n, 8.0 * n
+    else:
+        slots, nbytes = (SLOTS_GEN[gen] + SLOTS_DIST[dist]) * n, 4.0 * n
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
     t_alu = slots / (VALU_PEAK_TSLOTS * 1e12)
     return {"valu_tslots_s": round(slots / t / 1e12, 2), "valu_frac": round(t_alu / t, 4),
             "binding": "alu" if t_alu > t_hbm else "hbm",
@@ -423,6 +430,20 @@ def main():
                         "store_ceiling_frac": round(gbs / ceiling_gbs, 4),
                         "valu_tslots_s": rf["valu_tslots_s"], "valu_frac": rf["valu_frac"],
                         "binding": rf["binding"], "binding_frac": rf["binding_frac"]})
+    # float64 uniform fills (4 GiB each), measured beside the step: not part of
+    # the configured workload, so not in `value`
+    extra = []
+    if not args.only:
+        n64 = n // 2
+        for g in range(5):
+            ms = _time_events(stream, lambda: orng.orng_fill(g, 3, seed, 0, 0, n64, out, stream), 3)
+            rf = roofs(g, 3, n64, ms)
+            gbs = 8.0 * n64 / (ms * 1e-3) / 1e9
+            extra.append({"gen": inputs.GEN_NAMES[g], "dist": "f64_uniform", "ms": round(ms, 4),
+                          "gsamples_s": round(n64 / (ms * 1e-3) / 1e9, 2),
+                          "write_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                          "valu_frac": rf["valu_frac"], "binding": rf["binding"],
+                          "binding_frac": rf["binding_frac"]})
     # the dominant (longest) kernel of the step, against its binding roof
     dom = max(range(len(combos)), key=lambda k: per_kernel_ms[k])
     dk = kernels[dom]
@@ -455,6 +476,8 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
     }
+    if extra:
+        result["extra_kernels"] = extra
     del out
     torch.cuda.empty_cache()
 
