@@ -185,7 +185,8 @@ typedef struct {
  * h_reqs is host memory, copied before the call returns.  Output ranges of
  * different requests must not overlap.  Requests with n == 0 are skipped.
  * Errors: EINVAL / ERANGE as orng_fill for the first bad request (nothing is
- *         enqueued then); ENOMEM if the batch needs more than 2^28 tiles.
+ *         enqueued then); ENOMEM if the batch needs more than 2^28 tiles or
+ *         holds 2^32 or more requests.
  */
 int orng_fill_batched(const orng_req_t *h_reqs, size_t nreq, void *stream);
 

@@ -20,7 +20,9 @@
 // a context is reused only after the event of its previous launch.
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/orng.h"
@@ -238,6 +240,26 @@ void request_tiles(const orng_req_t &r, uint32_t unroll, uint32_t W, uint64_t *f
     *count = (spans + W - 1) / W;
 }
 
+// Contiguous ranges [begin(t), begin(t+1)) of [0, n) for up to eight host
+// threads (one for small n); run(f) calls f(t, begin, end) for every range,
+// range 0 on the caller's thread.
+struct Ranges {
+    size_t n, T;
+    explicit Ranges(size_t n_) : n(n_) {
+        const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+        T = n < 8192 ? 1 : std::min<size_t>({8, hw, n / 4096});
+    }
+    size_t begin(size_t t) const { return n * t / T; }
+    template <class F>
+    void run(F f) const {
+        std::vector<std::thread> th;
+        th.reserve(T - 1);
+        for (size_t t = 1; t < T; ++t) th.emplace_back([=, &f] { f(t, begin(t), begin(t + 1)); });
+        f(size_t(0), begin(0), begin(1));
+        for (auto &x : th) x.join();
+    }
+};
+
 static bool use_graphs() {
     static const bool on = [] {
         const char *e = getenv("ORNG_NO_GRAPH");
@@ -248,32 +270,53 @@ static bool use_graphs() {
 
 int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     if (nreq && !reqs) return ORNG_EINVAL;
-    for (size_t i = 0; i < nreq; ++i) {
-        const int st = validate_request(reqs[i]);
-        if (st != ORNG_OK) return st;
-    }
-    // requests with work, tile counts and prefix
-    std::vector<uint32_t> live;
-    live.reserve(nreq);
-    for (size_t i = 0; i < nreq; ++i)
-        if (reqs[i].n) live.push_back((uint32_t)i);
-    if (live.empty()) return ORNG_OK;
-    std::vector<uint64_t> fspan(live.size()), cnt(live.size());
-    std::vector<uint32_t> unr(live.size());
-    const orng_req_t &r0 = reqs[live[0]];
-    const uint32_t W = batch_wg((int)r0.gen, (int)r0.dist) / 64;
+    if (!nreq) return ORNG_OK;
+    if (nreq > 0xFFFFFFFFull) return ORNG_ENOMEM;  // the tile map holds 32-bit request numbers
+    // Host preparation in two parallel passes over contiguous ranges of the
+    // request list: (1) validate and tile every request, summing each range's
+    // tiles; then, after a scan over the ranges, (2) write each request's
+    // table row and its tiles' entries of the tile map.  Every request keeps
+    // its own row (one without work owns no tiles).
+    const Ranges rg(nreq);
+    std::unique_ptr<uint64_t[]> fspan(new uint64_t[nreq]), cnt(new uint64_t[nreq]);
+    std::unique_ptr<uint32_t[]> unr(new uint32_t[nreq]);
+    std::vector<uint64_t> range_tiles(rg.T + 1, 0);
+    std::vector<size_t> range_bad(rg.T, nreq);  // first invalid request of each range
+    std::vector<int> range_st(rg.T, ORNG_OK);
     uint32_t unroll_of[NGEN][NDIST];  // one table lookup per pair, not per request
     for (int g = 0; g < NGEN; ++g)
         for (int d = 0; d < NDIST; ++d)
             unroll_of[g][d] = g == G_TYCHE ? 64 : tuned_fill(g, d).b_unroll;
-    uint64_t tiles = 0;
-    for (size_t k = 0; k < live.size(); ++k) {
-        const orng_req_t &r = reqs[live[k]];
-        unr[k] = unroll_of[r.gen][r.dist];
-        request_tiles(r, unr[k], W, &fspan[k], &cnt[k]);
-        tiles += cnt[k];
-    }
+    // The workgroup shape, and so the tile size, follows the first request
+    // with work; this pass finds it before tiling.
+    size_t first_live = nreq;
+    for (size_t i = 0; i < nreq && first_live == nreq; ++i)
+        if (reqs[i].n && validate_request(reqs[i]) == ORNG_OK) first_live = i;
+    const uint32_t W =
+        first_live < nreq ? batch_wg((int)reqs[first_live].gen, (int)reqs[first_live].dist) / 64
+                          : 1;
+    rg.run([&](size_t t, size_t a, size_t b) {
+        uint64_t sum = 0;
+        for (size_t i = a; i < b; ++i) {
+            const int st = validate_request(reqs[i]);
+            if (st != ORNG_OK) { range_bad[t] = i; range_st[t] = st; return; }
+            cnt[i] = 0;
+            fspan[i] = 0;
+            unr[i] = 0;
+            if (!reqs[i].n) continue;
+            unr[i] = unroll_of[reqs[i].gen][reqs[i].dist];
+            request_tiles(reqs[i], unr[i], W, &fspan[i], &cnt[i]);
+            sum += cnt[i];
+        }
+        range_tiles[t + 1] = sum;
+    });
+    for (size_t t = 0; t < rg.T; ++t)
+        if (range_bad[t] < nreq) return range_st[t];  // ranges are in list order
+    for (size_t t = 0; t < rg.T; ++t) range_tiles[t + 1] += range_tiles[t];
+    const uint64_t tiles = range_tiles[rg.T];
+    if (tiles == 0) return ORNG_OK;
     if (tiles > (1ull << 28)) return ORNG_ENOMEM;
+    const orng_req_t &r0 = reqs[first_live];
 
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -285,7 +328,7 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
 #define ORNG_TRY(x) do { e = (x); if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; } } while (0)
     if (!c.done) ORNG_TRY(hipEventCreateWithFlags(&c.done, hipEventDisableTiming));
     else ORNG_TRY(hipEventSynchronize(c.done));  // staging and tables of its last use are free
-    ORNG_TRY(ensure_capacity(c, live.size(), tiles));
+    ORNG_TRY(ensure_capacity(c, nreq, tiles));
     if (!db->capture) ORNG_TRY(hipStreamCreateWithFlags(&db->capture, hipStreamNonBlocking));
 
     const BatchShape sh = batch_shape((int)r0.gen, (int)r0.dist, tiles);
@@ -297,30 +340,32 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     std::memset(hdr, 0, sizeof(BatchHdr));
     hdr->total_tiles = tiles;
     hdr->cursor = 0;
-    hdr->nreq = (uint32_t)live.size();
+    hdr->nreq = (uint32_t)nreq;
     hdr->chunk = sh.chunk;
     hdr->spans_per_tile = W;
-    uint64_t ts = 0;
-    for (size_t k = 0; k < live.size(); ++k) {
-        const orng_req_t &r = reqs[live[k]];
-        DevReq &d = dq[k];
-        const uint64_t kw = words_per_sample((int)r.dist);
-        d.out = static_cast<char *>(r.out);
-        d.p0 = r.offset * kw;  // positions and counts in stream words from here on
-        d.n = r.n * kw;
-        d.seed = r.seed;
-        d.first_span = fspan[k];
-        d.tile_start = ts;
-        d.ctr = r.ctr;
-        d.unroll = unr[k];
-        const uint64_t addr_words = reinterpret_cast<uintptr_t>(r.out) / 4;
-        const uint32_t delta = (uint32_t)((addr_words - d.p0) & 3u);
-        d.flags = r.gen | (r.dist << 4) | (delta << 8);
-        d.pad = 0;
-        std::fill_n(map + ts, cnt[k], (uint32_t)k);
-        ts += cnt[k];
-    }
-    ORNG_TRY(hipMemcpyAsync(c.d_buf, c.h_buf, sizeof(BatchHdr) + live.size() * sizeof(DevReq),
+    rg.run([&](size_t t, size_t a, size_t b) {
+        uint64_t ts = range_tiles[t];
+        for (size_t i = a; i < b; ++i) {
+            const orng_req_t &r = reqs[i];
+            const uint64_t kw = words_per_sample((int)r.dist);
+            DevReq &d = dq[i];
+            d.out = static_cast<char *>(r.out);
+            d.p0 = r.offset * kw;  // positions and counts in stream words from here on
+            d.n = r.n * kw;
+            d.seed = r.seed;
+            d.first_span = fspan[i];
+            d.tile_start = ts;
+            d.ctr = r.ctr;
+            d.unroll = unr[i];
+            const uint64_t addr_words = reinterpret_cast<uintptr_t>(r.out) / 4;
+            const uint32_t delta = (uint32_t)((addr_words - d.p0) & 3u);
+            d.flags = r.gen | (r.dist << 4) | (delta << 8);
+            d.pad = 0;
+            std::fill_n(map + ts, cnt[i], (uint32_t)i);
+            ts += cnt[i];
+        }
+    });
+    ORNG_TRY(hipMemcpyAsync(c.d_buf, c.h_buf, sizeof(BatchHdr) + nreq * sizeof(DevReq),
                             hipMemcpyHostToDevice, stream));
     ORNG_TRY(hipMemcpyAsync(c.d_buf + map_off, c.h_buf + map_off, tiles * sizeof(uint32_t),
                             hipMemcpyHostToDevice, stream));

@@ -122,6 +122,23 @@ def test_batched_validation_rejects_whole_batch(L, fn):
     assert f(None, 3, None) == EINVAL
 
 
+@pytest.mark.parametrize("fn", ["orng_fill_batched", "orng_fill_each"])
+def test_batched_validation_reports_the_first_bad_request(L, fn):
+    """Large lists are validated in parallel ranges; the status returned is
+    still that of the first bad request in list order."""
+    f = getattr(L, fn)
+    rows = [(0, 0, 0, 16, FAKE, 0)] * 20000
+    for first, second, want in [((15000, 9), (19000, 2**32 - 8), EINVAL),
+                                ((3000, 2**32 - 8), (17000, 9), ERANGE)]:
+        r = _reqs(rows)
+        for (i, what) in (first, second):
+            if what == 9:
+                r[i]["gen"] = 9
+            else:
+                r[i]["offset"] = what
+        assert f(r.ctypes.data, r.size, None) == want
+
+
 def test_launch_knob_validation(L):
     class cfg_t(C.Structure):
         _fields_ = [("wg_size", C.c_uint32), ("unroll", C.c_uint32), ("max_wgs", C.c_uint32),
