@@ -263,7 +263,7 @@ BD2_SLOTS = 37 + 26
 BD2_BYTES_PER_STEP = 64  # one launch per step: load and store x, y, vx, vy
 
 
-def bench_bd2(orng, inputs, stream, dev):
+def bench_bd2(orng, inputs, stream, dev, per_step_too=True):
     """The paper's 2-D Brownian dynamics run (10^6 particles, 10^4 steps):
     all steps in one launch vs one launch per step (the paper's structure)."""
     import torch
@@ -284,17 +284,19 @@ def bench_bd2(orng, inputs, stream, dev):
     orng.orng_bd2(p["pid0"], n, p["step0"], 10, p["dt"], p["gamma_over_m"], st[0], st[1], st[2],
                   st[3], 1, stream)  # warm-up
     fused = min(run(0) for _ in range(2))
-    per_step = run(1)
+    per_step = run(1) if per_step_too else None
     ps = n * T
     slots = BD2_SLOTS * ps
     del st
-    return {"n_particles": n, "n_steps": T, "fused_ms": round(fused, 3),
-            "per_step_launch_ms": round(per_step, 3),
-            "fused_particle_steps_per_s": round(ps / (fused * 1e-3), 1),
-            "fused_vs_per_step": round(per_step / fused, 3),
-            "fused_valu_tslots_s": round(slots / (fused * 1e-3) / 1e12, 2),
-            "fused_valu_frac": round(slots / (fused * 1e-3) / 1e12 / VALU_PEAK_TSLOTS, 4),
-            "per_step_gbs": round(BD2_BYTES_PER_STEP * ps / (per_step * 1e-3) / 1e9, 1)}
+    r = {"n_particles": n, "n_steps": T, "fused_ms": round(fused, 3),
+         "fused_particle_steps_per_s": round(ps / (fused * 1e-3), 1),
+         "fused_valu_tslots_s": round(slots / (fused * 1e-3) / 1e12, 2),
+         "fused_valu_frac": round(slots / (fused * 1e-3) / 1e12 / VALU_PEAK_TSLOTS, 4)}
+    if per_step is not None:
+        r.update({"per_step_launch_ms": round(per_step, 3),
+                  "fused_vs_per_step": round(per_step / fused, 3),
+                  "per_step_gbs": round(BD2_BYTES_PER_STEP * ps / (per_step * 1e-3) / 1e9, 1)})
+    return r
 
 
 def bench_serve(orng, inputs, stream, dev, bulk_rates=None):
@@ -358,6 +360,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-bd2", action="store_true")
+    ap.add_argument("--bd2-fused-only", action="store_true",
+                    help="skip the one-launch-per-step Brownian dynamics run (counter runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (counter calibration)")
     ap.add_argument("--walk-steps", type=int, default=0, help="shorter walk (profiling runs)")
@@ -508,7 +512,7 @@ def main():
         del pos, msd
 
     if not args.no_bd2:
-        result["bd2"] = bench_bd2(orng, inputs, stream, dev)
+        result["bd2"] = bench_bd2(orng, inputs, stream, dev, not args.bd2_fused_only)
 
     if not args.no_batched:
         result["batched"] = bench_batched(orng, inputs, stream, dev)
