@@ -29,7 +29,9 @@ CXXFLAGS = ["-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
 
 def build(force: bool = True) -> str:
     """Compile the oracle with g++ into ``oracle/liborng_oracle.so``."""
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+    srcs = [SRC, os.path.join(os.path.dirname(SRC), "orng_oracle.h")]
+    if not force and os.path.exists(LIB) and \
+            os.path.getmtime(LIB) >= max(os.path.getmtime(f) for f in srcs):
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.run(["g++", *CXXFLAGS, SRC, "-o", tmp], check=True)
@@ -43,8 +45,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build()
+        build(force=False)  # rebuilds when the sources are newer than the library
         L = C.CDLL(LIB)
         u32, u64, i32, vp, f32 = C.c_uint32, C.c_uint64, C.c_int, C.c_void_p, C.c_float
         P32, P64 = C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)
@@ -74,6 +75,7 @@ def lib():
             "oracle_brownian": (i32, [u64, u32, vp, u32, u32, u64, u32, f32, f32, vp, vp, u32,
                                       i32]),
             "oracle_u01_f64": (C.c_double, [u32, u32]),
+            "oracle_particle_streams": (i32, [i32, u64, u32, u32, u32, u32, vp, i32]),
             "oracle_bd2": (i32, [u64, vp, u32, u32, u32, C.c_double, C.c_double, vp, vp, vp, vp,
                                  i32]),
         }
@@ -276,3 +278,14 @@ def bd2(pid0, n_particles=None, ids=None, step0=1, n_steps=1, dt=1e-3, c=1.0, st
     if rc != 0:
         raise ValueError("oracle_bd2 rejected arguments (%d)" % rc)
     return st
+
+
+def particle_streams(gen, seed0, n_particles, draws, ctr0, n_iters, nthreads=None):
+    """(n_iters * n_particles * draws) uint32 words of the concatenated
+    per-particle micro-streams."""
+    out = np.empty(n_iters * n_particles * draws, np.uint32)
+    rc = lib().oracle_particle_streams(gen, seed0, n_particles, draws, ctr0, n_iters,
+                                       out.ctypes.data, nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_particle_streams rejected arguments (%d)" % rc)
+    return out

@@ -645,4 +645,31 @@ int oracle_bd2(uint64_t pid0, const uint32_t *ids, uint32_t count, uint32_t step
     return 0;
 }
 
+
+/* ---------------------------------------------------------------------------
+ * Parallel micro-streams for statistical testing (section 5.2, after the
+ * parallel-stream procedure it cites): each of n_particles particles draws a
+ * micro-stream of `draws` words per iteration from its own stream, keyed as in
+ * the paper's example (seed = particle id, counter = iteration); an
+ * iteration's micro-streams are concatenated in particle order, and the
+ * iterations follow one another.  Built from oracle_word, whose stream layout
+ * is pinned in the test-suite; the concatenation is checked against
+ * per-stream fills there.
+ * ------------------------------------------------------------------------- */
+int oracle_particle_streams(int gen, uint64_t seed0, uint32_t n_particles, uint32_t draws,
+                            uint32_t ctr0, uint32_t n_iters, uint32_t *out, int nthreads) {
+    if (!valid_gen(gen) || draws < 1 || draws > 16) return -1;
+    if (n_iters && (uint64_t)ctr0 + n_iters - 1 > 0xFFFFFFFFull) return -2;
+    if (n_particles && seed0 + (n_particles - 1) < seed0) return -2;
+    const uint64_t units = (uint64_t)n_iters * n_particles;
+    parallel_ranges(units, nthreads, [&](uint64_t a, uint64_t b, int) {
+        for (uint64_t u = a; u < b; ++u) {
+            const uint64_t t = u / n_particles, p = u % n_particles;
+            for (uint32_t k = 0; k < draws; ++k)
+                out[u * draws + k] = oracle_word(gen, seed0 + p, ctr0 + (uint32_t)t, k);
+        }
+    });
+    return 0;
+}
+
 } // extern "C"

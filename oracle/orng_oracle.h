@@ -104,6 +104,14 @@ int oracle_bd2(uint64_t pid0, const uint32_t *ids, uint32_t count, uint32_t step
                uint32_t n_steps, double dt, double c, double *x, double *y, double *vx,
                double *vy, int nthreads);
 
+/* --- parallel micro-streams (section 5.2) ---------------------------------- */
+/* out[((t * n_particles) + p) * draws + k] = word k of stream
+   (seed0 + p, ctr0 + t) of generator gen, for t < n_iters, p < n_particles,
+   k < draws.  Returns 0, -1 (gen, draws not in 1..16) or -2 (counter or
+   seed range overflows). */
+int oracle_particle_streams(int gen, uint64_t seed0, uint32_t n_particles, uint32_t draws,
+                            uint32_t ctr0, uint32_t n_iters, uint32_t *out, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif
