@@ -299,6 +299,36 @@ def bench_bd2(orng, inputs, stream, dev, per_step_too=True):
     return r
 
 
+# VALU slots per 3-word micro-stream (one stream per particle and iteration):
+# one counter block for Philox/Threefry (3 of its 4 words used); three
+# Squares words plus the y product; Tyche seeds an instance (20 MIX) and runs
+# 4 more (12 slots per MIX).
+PART_SLOTS_3 = {0: 38, 1: 128, 2: 109, 3: 3 + 3 * 13, 4: 24 * 12}
+
+
+def bench_particles(orng, inputs, stream, dev):
+    """Section 5.2's parallel-stream shape: 16,000 particles x 3 draws per
+    iteration, ~4 GiB of concatenated micro-streams per generator."""
+    import torch
+    P, D = 16000, 3
+    T = (1 << 30) // (P * D)
+    out = torch.empty(T * P * D, dtype=torch.int32, device=dev)
+    res = []
+    for g in range(5):
+        ms = _time_events(stream, lambda: orng.orng_particle_streams(g, 1, P, D, 1, T, out,
+                                                                     stream), 3)
+        words = T * P * D
+        t_hbm = 4.0 * words / (HBM_PEAK_GBS * 1e9)
+        t_alu = PART_SLOTS_3[g] * T * P / (VALU_PEAK_TSLOTS * 1e12)
+        res.append({"gen": inputs.GEN_NAMES[g], "ms": round(ms, 4),
+                    "write_gbs": round(4.0 * words / (ms * 1e-3) / 1e9, 1),
+                    "binding": "alu" if t_alu > t_hbm else "hbm",
+                    "binding_frac": round(max(t_alu, t_hbm) / (ms * 1e-3), 4)})
+    del out
+    torch.cuda.empty_cache()
+    return {"particles": P, "draws": D, "iterations": T, "words": T * P * D, "gens": res}
+
+
 def bench_serve(orng, inputs, stream, dev, bulk_rates=None):
     """Poisson arrivals (mean 5,000/s) of mixed fill requests, sizes
     log-uniform in [2^10, 2^26] words, four generator families x three
@@ -360,6 +390,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-bd2", action="store_true")
+    ap.add_argument("--no-particles", action="store_true")
     ap.add_argument("--bd2-fused-only", action="store_true",
                     help="skip the one-launch-per-step Brownian dynamics run (counter runs)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -513,6 +544,9 @@ def main():
 
     if not args.no_bd2:
         result["bd2"] = bench_bd2(orng, inputs, stream, dev, not args.bd2_fused_only)
+
+    if not args.no_particles:
+        result["particle_streams"] = bench_particles(orng, inputs, stream, dev)
 
     if not args.no_batched:
         result["batched"] = bench_batched(orng, inputs, stream, dev)

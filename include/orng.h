@@ -103,6 +103,24 @@ int orng_fill_multi(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t n_
                     uint64_t offset, uint64_t per_stream, void *d_out, void *stream);
 
 /*
+ * orng_particle_streams -- parallel micro-streams for statistical testing of
+ * parallel streams (section 5.2, after the procedure it cites):
+ *   out[(t * n_particles + p) * draws + k] = word k of stream
+ *                                           (seed0 + p, ctr0 + t)
+ * for t < n_iters, p < n_particles, k < draws: each particle draws a
+ * micro-stream of `draws` words per iteration from its own stream, keyed as
+ * in the paper's example (seed = particle id, counter = iteration); an
+ * iteration's micro-streams are concatenated in particle order.  Word k is
+ * orng_fill's word at position k of the same stream.
+ * d_out: device buffer of n_iters * n_particles * draws 32-bit words.
+ * Errors: EINVAL (gen, draws not in 1..16, NULL or misaligned d_out), ERANGE
+ *         (ctr0 + n_iters - 1 > 2^32 - 1, seed0 + n_particles - 1 overflows
+ *         64 bits).  n_particles = 0 or n_iters = 0 does nothing.
+ */
+int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particles, uint32_t draws,
+                          uint32_t ctr0, uint32_t n_iters, void *d_out, void *stream);
+
+/*
  * orng_brownian -- fused overdamped Brownian walk (paper section 4, Fig. 1;
  * section 5.1), all steps in one launch.
  * Particle i (0 <= i < n_particles) owns the Philox4x32-10 stream

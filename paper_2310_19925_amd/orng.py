@@ -71,6 +71,7 @@ def _load():
         "orng_fill_multi": [i32, i32, u64, u32, u32, u64, u64, vp, vp],
         "orng_brownian": [u64, u32, u32, u32, u64, u32, f32, f32, vp, vp, u32, vp],
         "orng_bd2": [u64, u32, u32, u32, C.c_double, C.c_double, vp, vp, vp, vp, u32, vp],
+        "orng_particle_streams": [i32, u64, u32, u32, u32, u32, vp, vp],
         "orng_normal_pairs": [vp, vp, u64, vp, vp, vp],
         "orng_fill_batched": [vp, C.c_size_t, vp],
         "orng_fill_each": [vp, C.c_size_t, vp],
@@ -148,6 +149,11 @@ def orng_bd2(pid0, n, step0, n_steps, dt, gamma_over_m, x, y, vx, vy, steps_per_
              stream=None):
     _check(_lib.orng_bd2(pid0, n, step0, n_steps, dt, gamma_over_m, _ptr(x), _ptr(y), _ptr(vx),
                          _ptr(vy), steps_per_launch, _stream(stream)), "orng_bd2")
+
+
+def orng_particle_streams(gen, seed0, n_particles, draws, ctr0, n_iters, out, stream=None):
+    _check(_lib.orng_particle_streams(gen, seed0, n_particles, draws, ctr0, n_iters, _ptr(out),
+                                      _stream(stream)), "orng_particle_streams")
 
 
 def orng_set_launch(wg_size=0, unroll=0, max_wgs=0, nontemporal=0):

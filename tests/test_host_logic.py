@@ -23,6 +23,7 @@ def L():
     lib.orng_brownian.argtypes = [u64, u32, u32, u32, u64, u32, f32, f32, vp, vp, u32, vp]
     lib.orng_normal_pairs.argtypes = [vp, vp, u64, vp, vp, vp]
     lib.orng_bd2.argtypes = [u64, u32, u32, u32, C.c_double, C.c_double, vp, vp, vp, vp, u32, vp]
+    lib.orng_particle_streams.argtypes = [i32, u64, u32, u32, u32, u32, vp, vp]
     lib.orng_fill_batched.argtypes = [vp, C.c_size_t, vp]
     lib.orng_fill_each.argtypes = [vp, C.c_size_t, vp]
     lib.orng_tune_load.argtypes = [C.c_char_p]
@@ -83,6 +84,18 @@ def test_bd2_validation(L):
     # nothing to do: no pointer is looked at
     assert L.orng_bd2(1, 0, 1, 5, 1e-3, 1.0, None, None, None, None, 0, None) == 0
     assert L.orng_bd2(1, 4, 1, 0, 1e-3, 1.0, None, None, None, None, 0, None) == 0
+
+
+def test_particle_streams_validation(L):
+    assert L.orng_particle_streams(5, 0, 10, 3, 0, 1, FAKE, None) == EINVAL
+    assert L.orng_particle_streams(0, 0, 10, 0, 0, 1, FAKE, None) == EINVAL
+    assert L.orng_particle_streams(0, 0, 10, 17, 0, 1, FAKE, None) == EINVAL
+    assert L.orng_particle_streams(0, 0, 10, 3, 2**32 - 1, 2, FAKE, None) == ERANGE
+    assert L.orng_particle_streams(0, 2**64 - 5, 10, 3, 0, 1, FAKE, None) == ERANGE
+    assert L.orng_particle_streams(0, 0, 10, 3, 0, 1, None, None) == EINVAL
+    assert L.orng_particle_streams(0, 0, 10, 3, 0, 1, FAKE + 2, None) == EINVAL
+    assert L.orng_particle_streams(0, 0, 0, 3, 0, 1, None, None) == 0
+    assert L.orng_particle_streams(0, 0, 10, 3, 0, 0, None, None) == 0
 
 
 def test_normal_pairs_validation(L):
