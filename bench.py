@@ -79,14 +79,14 @@ def roofs(gen, dist, n, ms):
 # calibration factors a 1 GiB device copy gives for each counter.  Valid only
 # for the kernel sources and launch table they were measured on: bench.py
 # reports null traffic when the hash of those sources differs.
-TRAFFIC_SRC_SHA = "d4bb6d7e71669f40"
-TRAFFIC_FACTORS = (1.999922278563641, 1.0)  # FETCH, WRITE
+TRAFFIC_SRC_SHA = "692ccc0adbc58f5f"
+TRAFFIC_FACTORS = (1.9999251393683242, 1.0)  # FETCH, WRITE
 TRAFFIC_KIB = {
-    (0, 0): (65.125, 4194304.0), (0, 1): (33.0, 4194451.75), (0, 2): (54.4375, 4194319.5),
-    (1, 0): (39.625, 4194304.0), (1, 1): (39.125, 4194323.875), (1, 2): (41.5, 4194304.25),
-    (2, 0): (33.5, 4194322.875), (2, 1): (35.625, 4194338.375), (2, 2): (40.0, 4194304.0),
-    (3, 0): (29.0, 4194304.0), (3, 1): (25.0, 4194405.75), (3, 2): (83.0625, 4194304.0),
-    (4, 0): (38.3125, 4194304.0), (4, 1): (26.9375, 4194304.0), (4, 2): (40.75, 4194398.625),
+    (0, 0): (63.1875, 4194304.0), (0, 1): (32.5, 4194563.125), (0, 2): (58.0625, 4194328.5), (0, 3): (34.0625, 4801733.875),
+    (1, 0): (37.3125, 4194304.0), (1, 1): (42.75, 4194329.875), (1, 2): (35.625, 4194304.5), (1, 3): (31.5, 4201499.875),
+    (2, 0): (34.5, 4194323.625), (2, 1): (35.5625, 4194333.0), (2, 2): (40.0, 4194304.0), (2, 3): (31.5, 4194336.0),
+    (3, 0): (32.0, 4194321.375), (3, 1): (32.0, 4194379.125), (3, 2): (79.4375, 4194330.125), (3, 3): (33.0, 4201655.875),
+    (4, 0): (39.9375, 4194304.0), (4, 1): (33.625, 4194304.0), (4, 2): (45.5625, 4194319.875), (4, 3): (30.875, 4203251.625),
 }
 
 
@@ -161,6 +161,23 @@ def _time_events(stream, fn, reps):
         ms.append(a.elapsed_time(b))
     ms.sort()
     return ms[len(ms) // 2]
+
+
+def bench_plain_multi(orng, inputs, stream, dev):
+    """The configured plain multi-stream fill: one seed (42), 2^20 streams
+    (counters 0..2^20-1) of 4 words each, u32 and float32 uniform; one
+    launch, so microseconds."""
+    import torch
+    ns, per = inputs.PLAIN_STREAMS, inputs.PLAIN_PER_STREAM
+    n = ns * per
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    res = {"n_streams": ns, "per_stream": per}
+    for d, name in ((0, "u32"), (1, "f32_uniform")):
+        ms = _time_events(stream, lambda: orng.orng_fill_multi(0, d, inputs.PLAIN_SEED, 0, ns, 0,
+                                                               per, out, stream), 21)
+        res[name] = {"us": round(ms * 1e3, 2), "gsamples_s": round(n / (ms * 1e-3) / 1e9, 2)}
+    del out
+    return res
 
 
 def bench_batched(orng, inputs, stream, dev):
@@ -391,6 +408,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-bd2", action="store_true")
     ap.add_argument("--no-particles", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--bd2-fused-only", action="store_true",
                     help="skip the one-launch-per-step Brownian dynamics run (counter runs)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -544,6 +562,9 @@ def main():
 
     if not args.no_bd2:
         result["bd2"] = bench_bd2(orng, inputs, stream, dev, not args.bd2_fused_only)
+
+    if not args.no_plain:
+        result["plain_multi"] = bench_plain_multi(orng, inputs, stream, dev)
 
     if not args.no_particles:
         result["particle_streams"] = bench_particles(orng, inputs, stream, dev)
