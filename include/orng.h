@@ -270,7 +270,8 @@ typedef struct {
     uint64_t arena_peak_bytes;
     uint32_t active_peak;   /* most requests resident at once */
     uint32_t queued;        /* waiting for admission now */
-    double latency_p50_ms, latency_p99_ms, latency_mean_ms; /* submit -> done, completed */
+    double latency_p50_ms, latency_p99_ms, latency_mean_ms; /* submit -> done, nearest rank,
+                                                                over the latest 2^20 completed */
     double first_submit_to_last_done_s;
 } orng_serve_stats_t;
 

@@ -19,7 +19,9 @@
 // A small ring of such contexts per device lets consecutive calls overlap:
 // a context is reused only after the event of its previous launch.
 #include <algorithm>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -240,23 +242,75 @@ void request_tiles(const orng_req_t &r, uint32_t unroll, uint32_t W, uint64_t *f
     *count = (spans + W - 1) / W;
 }
 
+// Host worker threads for the batched path's preparation passes: started on
+// first use and kept (detached, waiting on a condition variable) until the
+// process ends, so a call pays a wake-up instead of thread creation.  One
+// job at a time; run(T, f) calls f(t) for t in [0, T), t = 0 on the caller.
+class HostPool {
+  public:
+    static HostPool &get() {
+        static HostPool *p = new HostPool();  // never destroyed: workers outlive main
+        return *p;
+    }
+    size_t size() const { return workers_ + 1; }
+    template <class F>
+    void run(size_t T, F f) {
+        T = std::min(T, size());
+        if (T <= 1) { f(size_t(0)); return; }
+        std::lock_guard<std::mutex> one(job_mu_);  // one job at a time
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            job_ = [&f](size_t t) { f(t); };
+            parts_ = T;
+            pending_ = T - 1;
+            ++gen_;
+        }
+        cv_.notify_all();
+        f(size_t(0));
+        std::unique_lock<std::mutex> lk(mu_);
+        done_.wait(lk, [&] { return pending_ == 0; });
+        job_ = nullptr;
+    }
+
+  private:
+    HostPool() {
+        const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+        workers_ = std::min<size_t>(7, hw > 1 ? hw - 1 : 0);
+        for (size_t w = 1; w <= workers_; ++w) std::thread([this, w] { loop(w); }).detach();
+    }
+    void loop(size_t w) {
+        uint64_t seen = 0;
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            cv_.wait(lk, [&] { return gen_ != seen; });
+            seen = gen_;
+            if (w >= parts_) continue;
+            auto job = job_;
+            lk.unlock();
+            job(w);
+            lk.lock();
+            if (--pending_ == 0) done_.notify_one();
+        }
+    }
+    size_t workers_ = 0;
+    std::mutex job_mu_, mu_;
+    std::condition_variable cv_, done_;
+    std::function<void(size_t)> job_;
+    size_t parts_ = 0, pending_ = 0;
+    uint64_t gen_ = 0;
+};
+
 // Contiguous ranges [begin(t), begin(t+1)) of [0, n) for up to eight host
-// threads (one for small n); run(f) calls f(t, begin, end) for every range,
-// range 0 on the caller's thread.
+// threads (one for small n); run(f) calls f(t, begin, end) for every range.
 struct Ranges {
     size_t n, T;
     explicit Ranges(size_t n_) : n(n_) {
-        const size_t hw = std::max(1u, std::thread::hardware_concurrency());
-        T = n < 8192 ? 1 : std::min<size_t>({8, hw, n / 4096});
+        T = n < 8192 ? 1 : std::min<size_t>(HostPool::get().size(), n / 4096);
     }
     size_t begin(size_t t) const { return n * t / T; }
     template <class F>
     void run(F f) const {
-        std::vector<std::thread> th;
-        th.reserve(T - 1);
-        for (size_t t = 1; t < T; ++t) th.emplace_back([=, &f] { f(t, begin(t), begin(t + 1)); });
-        f(size_t(0), begin(0), begin(1));
-        for (auto &x : th) x.join();
+        HostPool::get().run(T, [&](size_t t) { f(t, begin(t), begin(t + 1)); });
     }
 };
 
