@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "orng_oracle.cc")
 LIB = os.path.join(HERE, "liborng_oracle.so")
 
-PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE = range(5)
+PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE, THREEFRY4X32_13, THREEFRY2X64_13 = range(7)
 U32, F32_UNIFORM, F32_NORMAL, F64_UNIFORM = range(4)
 GENS = (PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE)
 DISTS = (U32, F32_UNIFORM, F32_NORMAL)  # the float32/u32 set; F64_UNIFORM is separate
@@ -53,6 +53,8 @@ def lib():
             "oracle_philox4x32_10": (None, [P32, P32, P32]),
             "oracle_threefry4x32_20": (None, [P32, P32, P32]),
             "oracle_threefry2x64_20": (None, [P64, P64, P64]),
+            "oracle_threefry4x32_13": (None, [P32, P32, P32]),
+            "oracle_threefry2x64_13": (None, [P64, P64, P64]),
             "oracle_squares32": (u32, [u64, u64]),
             "oracle_squares_key": (u64, [u64]),
             "oracle_tyche_mix": (None, [P32]),
@@ -112,6 +114,20 @@ def threefry2x64_20(ctr, key):
     c = (C.c_uint64 * 2)(*[int(v) & (2**64 - 1) for v in ctr])
     k = (C.c_uint64 * 2)(*[int(v) & (2**64 - 1) for v in key])
     lib().oracle_threefry2x64_20(c, k, out)
+    return list(out)
+
+
+def threefry2x64_13(ctr, key):
+    out = (C.c_uint64 * 2)()
+    c = (C.c_uint64 * 2)(*[int(v) & (2**64 - 1) for v in ctr])
+    k = (C.c_uint64 * 2)(*[int(v) & (2**64 - 1) for v in key])
+    lib().oracle_threefry2x64_13(c, k, out)
+    return list(out)
+
+
+def threefry4x32_13(ctr, key):
+    out = (C.c_uint32 * 4)()
+    lib().oracle_threefry4x32_13(_arr32(ctr), _arr32(key), out)
     return list(out)
 
 

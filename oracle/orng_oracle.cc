@@ -117,6 +117,7 @@ const uint64_t TYCHE_TILE = 16384, TYCHE_LANES = 64, TYCHE_BLOCKS = 64;
  *   Threefry4x32-20 : counter (p/4, ctr, 0, 0), key (lo seed, hi seed, 0, 0)
  *   Threefry2x64-20 : counter (p/4, ctr) as 64-bit words, key (seed, 0);
  *                     the four 32-bit words are lo X0, hi X0, lo X1, hi X1
+ *   the 13-round Threefry variants: as their 20-round forms
  * word(p) is word p mod 4 of that block.
  * ------------------------------------------------------------------------- */
 void counter_block(int gen, uint64_t seed, uint32_t ctr, uint64_t b, uint32_t out[4]) {
@@ -125,15 +126,17 @@ void counter_block(int gen, uint64_t seed, uint32_t ctr, uint64_t b, uint32_t ou
         uint32_t c[4] = {(uint32_t)b, ctr, 0u, 0u};
         uint32_t k[2] = {lo, hi};
         oracle_philox4x32_10(c, k, out);
-    } else if (gen == OR_THREEFRY4X32) {
+    } else if (gen == OR_THREEFRY4X32 || gen == OR_THREEFRY4X32_13) {
         uint32_t c[4] = {(uint32_t)b, ctr, 0u, 0u};
         uint32_t k[4] = {lo, hi, 0u, 0u};
-        oracle_threefry4x32_20(c, k, out);
-    } else { /* OR_THREEFRY2X64 */
+        if (gen == OR_THREEFRY4X32) oracle_threefry4x32_20(c, k, out);
+        else oracle_threefry4x32_13(c, k, out);
+    } else { /* OR_THREEFRY2X64, OR_THREEFRY2X64_13 */
         uint64_t c[2] = {b, (uint64_t)ctr};
         uint64_t k[2] = {seed, 0ull};
         uint64_t r[2];
-        oracle_threefry2x64_20(c, k, r);
+        if (gen == OR_THREEFRY2X64) oracle_threefry2x64_20(c, k, r);
+        else oracle_threefry2x64_13(c, k, r);
         out[0] = (uint32_t)r[0];
         out[1] = (uint32_t)(r[0] >> 32);
         out[2] = (uint32_t)r[1];
@@ -213,7 +216,7 @@ void samples_range(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t p0, 
     }
 }
 
-bool valid_gen(int g) { return g >= OR_PHILOX && g <= OR_TYCHE; }
+bool valid_gen(int g) { return g >= OR_PHILOX && g <= OR_THREEFRY2X64_13; }
 bool valid_dist(int d) { return d >= OR_U32 && d <= OR_F64_UNIFORM; }
 /* bytes per sample, and stream positions (words) per sample */
 uint64_t sample_bytes(int dist) { return dist == OR_F64_UNIFORM ? 8 : 4; }
@@ -251,13 +254,16 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
     std::memcpy(out, x, sizeof x);
 }
 
-void oracle_threefry4x32_20(const uint32_t ctr[4], const uint32_t key[4], uint32_t out[4]) {
+/* R rounds of Threefry4x32: the key is injected before round 0 and after
+   every fourth round (after round 4, 8, ...), so a round count that is not
+   a multiple of four ends on a plain round. */
+static void threefry4x32_r(const uint32_t ctr[4], const uint32_t key[4], int R, uint32_t out[4]) {
     uint32_t ks[5];
     ks[4] = SKEIN_PARITY32;
     for (int i = 0; i < 4; ++i) { ks[i] = key[i]; ks[4] ^= key[i]; }
     uint32_t x[4];
     for (int i = 0; i < 4; ++i) x[i] = ctr[i] + ks[i];
-    for (int r = 0; r < 20; ++r) {
+    for (int r = 0; r < R; ++r) {
         const unsigned ra = TF4_ROT[r % 8][0], rb = TF4_ROT[r % 8][1];
         if (r % 2 == 0) {
             x[0] += x[1]; x[1] = rotl32(x[1], ra) ^ x[0];
@@ -275,10 +281,23 @@ void oracle_threefry4x32_20(const uint32_t ctr[4], const uint32_t key[4], uint32
     std::memcpy(out, x, sizeof x);
 }
 
-void oracle_threefry2x64_20(const uint64_t ctr[2], const uint64_t key[2], uint64_t out[2]) {
+void oracle_threefry4x32_20(const uint32_t ctr[4], const uint32_t key[4], uint32_t out[4]) {
+    threefry4x32_r(ctr, key, 20, out);
+}
+
+/* The 13-round variants: the same rounds, rotations and key schedule,
+   stopped after round 13 (after the injection that follows round 12).
+   Pinned like their 20-round forms: Threefry2x64-13 against rocRAND's engine
+   instantiated with 13 rounds; Threefry4x32-13 through the big-integer
+   transcription run with 13 rounds under both mixing schedules. */
+void oracle_threefry4x32_13(const uint32_t ctr[4], const uint32_t key[4], uint32_t out[4]) {
+    threefry4x32_r(ctr, key, 13, out);
+}
+
+static void threefry2x64_r(const uint64_t ctr[2], const uint64_t key[2], int R, uint64_t out[2]) {
     const uint64_t ks[3] = {key[0], key[1], SKEIN_PARITY64 ^ key[0] ^ key[1]};
     uint64_t x0 = ctr[0] + ks[0], x1 = ctr[1] + ks[1];
-    for (int r = 0; r < 20; ++r) {
+    for (int r = 0; r < R; ++r) {
         x0 += x1;
         x1 = rotl64(x1, TF2_ROT[r % 8]) ^ x0;
         if (r % 4 == 3) {
@@ -289,6 +308,14 @@ void oracle_threefry2x64_20(const uint64_t ctr[2], const uint64_t key[2], uint64
     }
     out[0] = x0;
     out[1] = x1;
+}
+
+void oracle_threefry2x64_20(const uint64_t ctr[2], const uint64_t key[2], uint64_t out[2]) {
+    threefry2x64_r(ctr, key, 20, out);
+}
+
+void oracle_threefry2x64_13(const uint64_t ctr[2], const uint64_t key[2], uint64_t out[2]) {
+    threefry2x64_r(ctr, key, 13, out);
 }
 
 uint32_t oracle_squares32(uint64_t ctr, uint64_t key) {

@@ -40,13 +40,16 @@ extern "C" {
 
 /* generator and distribution codes (same numbering as the public API; the
    numbers are part of the interface, not shared code) */
-enum { OR_PHILOX = 0, OR_THREEFRY4X32 = 1, OR_THREEFRY2X64 = 2, OR_SQUARES = 3, OR_TYCHE = 4 };
+enum { OR_PHILOX = 0, OR_THREEFRY4X32 = 1, OR_THREEFRY2X64 = 2, OR_SQUARES = 3, OR_TYCHE = 4,
+       OR_THREEFRY4X32_13 = 5, OR_THREEFRY2X64_13 = 6 };
 enum { OR_U32 = 0, OR_F32_UNIFORM = 1, OR_F32_NORMAL = 2, OR_F64_UNIFORM = 3 };
 
 /* --- raw generator cores ------------------------------------------------ */
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void oracle_threefry4x32_20(const uint32_t ctr[4], const uint32_t key[4], uint32_t out[4]);
 void oracle_threefry2x64_20(const uint64_t ctr[2], const uint64_t key[2], uint64_t out[2]);
+void oracle_threefry4x32_13(const uint32_t ctr[4], const uint32_t key[4], uint32_t out[4]);
+void oracle_threefry2x64_13(const uint64_t ctr[2], const uint64_t key[2], uint64_t out[2]);
 uint32_t oracle_squares32(uint64_t ctr, uint64_t key);
 uint64_t oracle_squares_key(uint64_t seed);
 void oracle_tyche_mix(uint32_t st[4]);             /* st = {a, b, c, d}, in place */

@@ -74,6 +74,47 @@ def test_threefry4x32_oracle_vs_published_schedule(O):
         assert O.threefry4x32_20(c, k) == S.threefry4x32(c, k, schedule="every_round")
 
 
+def test_threefry2x64_13_vs_rocrand(O, rocrand_xcheck):
+    """The 13-round variant against rocRAND's engine template instantiated
+    with 13 rounds."""
+    r = random.Random(12)
+    cases = [([r.getrandbits(64), r.getrandbits(64)], [r.getrandbits(64), r.getrandbits(64)])
+             for _ in range(2000)]
+    lines = ["V %d %d %d %d" % (k[0], k[1], c[0], c[1]) for c, k in cases]
+    got = run_xcheck(rocrand_xcheck, lines)
+    for (c, k), g in zip(cases, got):
+        assert O.threefry2x64_13(c, k) == g
+
+
+def test_threefry4x32_13_two_step_pin(O, rocrand_xcheck):
+    """13 rounds: the transcription under rocRAND's schedule equals rocRAND's
+    engine template with 13 rounds, and under the published schedule equals
+    the oracle."""
+    cases = _rand_cases(2000, 13)
+    lines = ["U %d %d %d %d %d %d %d %d" % (*k, *c) for c, k in cases]
+    got = run_xcheck(rocrand_xcheck, lines)
+    for (c, k), g in zip(cases, got):
+        assert S.threefry4x32(c, k, rounds=13, schedule="every_second_round") == g
+        assert O.threefry4x32_13(c, k) == S.threefry4x32(c, k, rounds=13, schedule="every_round")
+
+
+M32 = 0xFFFFFFFF
+
+
+def test_threefry_13_round_streams(O):
+    """Generators 5 and 6 lay out their 13-round blocks exactly as generators 1
+    and 2 lay out their 20-round blocks, and the two round counts differ."""
+    seed, ctr = 0x0123456789ABCDEF, 77
+    for b in (0, 1, 5, 2**30 - 1):
+        w5 = O.fill(5, O.U32, seed, ctr, 4 * b, 4)
+        assert list(w5) == O.threefry4x32_13([b, ctr, 0, 0], [seed & M32, seed >> 32, 0, 0])
+        w6 = O.fill(6, O.U32, seed, ctr, 4 * b, 4)
+        x = O.threefry2x64_13([b, ctr], [seed, 0])
+        assert list(w6) == [x[0] & M32, x[0] >> 32, x[1] & M32, x[1] >> 32]
+        assert list(w5) != list(O.fill(1, O.U32, seed, ctr, 4 * b, 4))
+        assert list(w6) != list(O.fill(2, O.U32, seed, ctr, 4 * b, 4))
+
+
 def test_threefry4x32_schedules_really_differ(O):
     # guards the two-step pin: if the schedules coincided it would prove nothing
     c, k = [1, 2, 3, 4], [5, 6, 7, 8]
