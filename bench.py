@@ -51,7 +51,11 @@ VALU_PEAK_TSLOTS = 256 * 64 * 2.4e9 / 1e12
 #   Tyche: one MIX (4 add, 4 xor, 4 rotate) per word + 20 MIX per 256 words (lane init)
 #   f32 uniform: shift + convert + scale = 1 + 2 x 0.5
 #   f32 normal, per pair: 16 integer ops, 37 fp32 ops, rcp + rsq = 36.5 slots
-SLOTS_GEN = {0: 38 / 4, 1: 128 / 4, 2: 109 / 4, 3: 13 + 3 / 4, 4: 12 + 20 * 12 / 256}
+#   Threefry4x32-13: 11 full rounds x 6 + rounds 1-2 (7) + counter add 1 + 3
+#     injections x 2 (no injection after round 13): 80 / 4 words
+#   Threefry2x64-13: 12 rounds x 5 + round 1 (3) + counter add 1 + 3 x 2: 70 / 4 words
+SLOTS_GEN = {0: 38 / 4, 1: 128 / 4, 2: 109 / 4, 3: 13 + 3 / 4, 4: 12 + 20 * 12 / 256,
+             5: 80 / 4, 6: 70 / 4}
 SLOTS_DIST = {0: 0.0, 1: 2.0, 2: 36.5 / 2}
 # float64 uniform: two words per sample, then shift, two conversions, one
 # exact fma and one scaling (float64 operations: one slot each at the
@@ -484,16 +488,18 @@ def main():
                         "valu_tslots_s": rf["valu_tslots_s"], "valu_frac": rf["valu_frac"],
                         "binding": rf["binding"], "binding_frac": rf["binding_frac"]})
     # float64 uniform fills (4 GiB each), measured beside the step: not part of
-    # the configured workload, so not in `value`
+    # the configured workload, so not in `value`;
+    # and the 13-round Threefry variants (4 GiB each)
     extra = []
     if not args.only:
-        n64 = n // 2
-        for g in range(5):
-            ms = _time_events(stream, lambda: orng.orng_fill(g, 3, seed, 0, 0, n64, out, stream), 3)
-            rf = roofs(g, 3, n64, ms)
-            gbs = 8.0 * n64 / (ms * 1e-3) / 1e9
-            extra.append({"gen": inputs.GEN_NAMES[g], "dist": "f64_uniform", "ms": round(ms, 4),
-                          "gsamples_s": round(n64 / (ms * 1e-3) / 1e9, 2),
+        cases = [(g, 3) for g in range(7)] + [(g, d) for g in (5, 6) for d in range(3)]
+        for g, d in cases:
+            ns = n // 2 if d == 3 else n
+            ms = _time_events(stream, lambda: orng.orng_fill(g, d, seed, 0, 0, ns, out, stream), 3)
+            rf = roofs(g, d, ns, ms)
+            gbs = 4.0 * n / (ms * 1e-3) / 1e9
+            extra.append({"gen": inputs.GEN_NAMES[g], "dist": inputs.DIST_NAMES[d],
+                          "ms": round(ms, 4), "gsamples_s": round(ns / (ms * 1e-3) / 1e9, 2),
                           "write_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                           "valu_frac": rf["valu_frac"], "binding": rf["binding"],
                           "binding_frac": rf["binding_frac"]})

@@ -42,7 +42,9 @@ enum {
     ORNG_THREEFRY4X32_20 = 1,
     ORNG_THREEFRY2X64_20 = 2,
     ORNG_SQUARES32 = 3,
-    ORNG_TYCHE = 4
+    ORNG_TYCHE = 4,
+    ORNG_THREEFRY4X32_13 = 5, /* the Threefry rounds stopped after round 13 */
+    ORNG_THREEFRY2X64_13 = 6
 };
 
 /* distributions; samples are 4 bytes, 8 for ORNG_F64_UNIFORM */
@@ -79,6 +81,8 @@ enum {
  *   Threefry4x32-20: same counter, key (lo32 seed, hi32 seed, 0, 0)
  *   Threefry2x64-20: counter (p/4, ctr) as 64-bit words, key (seed, 0);
  *                    words lo X0, hi X0, lo X1, hi X1
+ *   Threefry4x32-13, Threefry2x64-13: as their 20-round forms, with the
+ *                    key injections after rounds 4, 8 and 12 and 13 rounds
  *   Squares32      : squares32(counter (ctr << 32) | p, key K(seed)),
  *                    K = SplitMix64 output step of seed, low bit set
  *   Tyche          : tiles of 16384 words; word p of tile t = p / 16384,

@@ -222,7 +222,7 @@ static void *batched_kernel(const BatchShape &s) {
 }
 
 int validate_request(const orng_req_t &r) {
-    if (r.gen > ORNG_TYCHE || r.dist > ORNG_F64_UNIFORM || r.flags != 0) return ORNG_EINVAL;
+    if (r.gen > ORNG_THREEFRY2X64_13 || r.dist > ORNG_F64_UNIFORM || r.flags != 0) return ORNG_EINVAL;
     const uint64_t k = words_per_sample((int)r.dist), lim = sample_limit((int)r.dist);
     if (r.offset > lim || r.n > lim - r.offset) return ORNG_ERANGE;
     if (r.n == 0) return ORNG_OK;

@@ -22,9 +22,10 @@
 
 namespace orng {
 
-enum GenId : int { G_PHILOX = 0, G_TF4X32 = 1, G_TF2X64 = 2, G_SQUARES = 3, G_TYCHE = 4 };
+enum GenId : int { G_PHILOX = 0, G_TF4X32 = 1, G_TF2X64 = 2, G_SQUARES = 3, G_TYCHE = 4,
+                   G_TF4X32_13 = 5, G_TF2X64_13 = 6 };
 enum DistId : int { D_U32 = 0, D_UNIFORM = 1, D_NORMAL = 2, D_F64U = 3 };
-constexpr int NGEN = 5, NDIST = 4;
+constexpr int NGEN = 7, NDIST = 4;
 
 // Per-launch key material, uniform across the grid.
 struct KeySched {
@@ -126,14 +127,22 @@ __device__ __forceinline__ void tf4_quad(uint32_t &x0, uint32_t &x1, uint32_t &x
     tf4_inject<S>(x0, x1, x2, x3, ks);
 }
 
+// NR = 20 (five quads) or 13 (three quads, then round 12 with no injection
+// after it).
+template <int NR>
 __device__ __forceinline__ void tf4_block(uint32_t c0, uint32_t c1, const KeySched &ks,
                                           uint32_t o[4]) {
+    static_assert(NR == 20 || NR == 13, "Threefry4x32 round count");
     uint32_t x0 = c0 + ks.ks4[0], x1 = c1 + ks.ks4[1], x2 = ks.ks4[2], x3 = ks.ks4[3];
     tf4_quad<1>(x0, x1, x2, x3, ks);
     tf4_quad<2>(x0, x1, x2, x3, ks);
     tf4_quad<3>(x0, x1, x2, x3, ks);
-    tf4_quad<4>(x0, x1, x2, x3, ks);
-    tf4_quad<5>(x0, x1, x2, x3, ks);
+    if constexpr (NR == 20) {
+        tf4_quad<4>(x0, x1, x2, x3, ks);
+        tf4_quad<5>(x0, x1, x2, x3, ks);
+    } else {
+        tf4_round<12>(x0, x1, x2, x3);
+    }
     o[0] = x0; o[1] = x1; o[2] = x2; o[3] = x3;
 }
 
@@ -177,15 +186,23 @@ __device__ __forceinline__ void tf2_quad(uint64_t &x0, uint64_t &x1, const KeySc
     x1 += ks.ks2[(S + 1) % 3] + (uint64_t)S;
 }
 
+// NR = 20 (five quads) or 13 (three quads, then round 12 with no injection
+// after it; rotation constants repeat with period 8).
+template <int NR>
 __device__ __forceinline__ void tf2_block(uint32_t c0, uint32_t c1, const KeySched &ks,
                                           uint32_t o[4]) {
+    static_assert(NR == 20 || NR == 13, "Threefry2x64 round count");
     uint64_t x0 = (uint64_t)c0 + ks.ks2[0];
     uint64_t x1 = (uint64_t)c1 + ks.ks2[1];
     tf2_quad<1>(x0, x1, ks);
     tf2_quad<2>(x0, x1, ks);
     tf2_quad<3>(x0, x1, ks);
-    tf2_quad<4>(x0, x1, ks);
-    tf2_quad<5>(x0, x1, ks);
+    if constexpr (NR == 20) {
+        tf2_quad<4>(x0, x1, ks);
+        tf2_quad<5>(x0, x1, ks);
+    } else {
+        tf2_round<16>(x0, x1);  // round 12: rotation constant index 12 mod 8 = 4
+    }
     o[0] = (uint32_t)x0; o[1] = (uint32_t)(x0 >> 32);
     o[2] = (uint32_t)x1; o[3] = (uint32_t)(x1 >> 32);
 }
@@ -424,9 +441,13 @@ __device__ __forceinline__ void counter_block(uint32_t blk, uint32_t ctr, const 
     if constexpr (G == G_PHILOX) {
         philox_block(blk, ctr, ks, w);
     } else if constexpr (G == G_TF4X32) {
-        tf4_block(blk, ctr, ks, w);
+        tf4_block<20>(blk, ctr, ks, w);
     } else if constexpr (G == G_TF2X64) {
-        tf2_block(blk, ctr, ks, w);
+        tf2_block<20>(blk, ctr, ks, w);
+    } else if constexpr (G == G_TF4X32_13) {
+        tf4_block<13>(blk, ctr, ks, w);
+    } else if constexpr (G == G_TF2X64_13) {
+        tf2_block<13>(blk, ctr, ks, w);
     } else {  // G_SQUARES
         squares_block(blk, ctr, ks.sqkey, w);
     }

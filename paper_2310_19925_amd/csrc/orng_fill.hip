@@ -120,6 +120,8 @@ static void *pick_kernel(int gen, int dist, bool units, bool nt) {
     case G_TF4X32: return pick_d<G_TF4X32>(dist, units, nt);
     case G_TF2X64: return pick_d<G_TF2X64>(dist, units, nt);
     case G_SQUARES: return pick_d<G_SQUARES>(dist, units, nt);
+    case G_TF4X32_13: return pick_d<G_TF4X32_13>(dist, units, nt);
+    case G_TF2X64_13: return pick_d<G_TF2X64_13>(dist, units, nt);
     default: return pick_d<G_TYCHE>(dist, units, nt);
     }
 }

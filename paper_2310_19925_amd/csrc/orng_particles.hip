@@ -93,7 +93,7 @@ using namespace orng;
 extern "C" int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particles,
                                      uint32_t draws, uint32_t ctr0, uint32_t n_iters,
                                      void *d_out, void *stream) {
-    if (gen < ORNG_PHILOX4X32_10 || gen > ORNG_TYCHE || draws < 1 || draws > 16)
+    if (gen < ORNG_PHILOX4X32_10 || gen > ORNG_THREEFRY2X64_13 || draws < 1 || draws > 16)
         return ORNG_EINVAL;
     if (n_iters && (uint64_t)ctr0 + n_iters - 1 > 0xFFFFFFFFull) return ORNG_ERANGE;
     if (n_particles && seed0 + (n_particles - 1) < seed0) return ORNG_ERANGE;
@@ -121,6 +121,8 @@ extern "C" int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particl
     case G_TF4X32: kern = ORNG_PK(G_TF4X32); break;
     case G_TF2X64: kern = ORNG_PK(G_TF2X64); break;
     case G_SQUARES: kern = ORNG_PK(G_SQUARES); break;
+    case G_TF4X32_13: kern = ORNG_PK(G_TF4X32_13); break;
+    case G_TF2X64_13: kern = ORNG_PK(G_TF2X64_13); break;
     default: kern = ORNG_PK(G_TYCHE); break;
     }
 #undef ORNG_PK

@@ -202,6 +202,8 @@ __device__ __forceinline__ void process_span_any(int gen, int dist, const KeySch
         ORNG_CASE(2, 0) ORNG_CASE(2, 1) ORNG_CASE(2, 2) ORNG_CASE(2, 3)
         ORNG_CASE(3, 0) ORNG_CASE(3, 1) ORNG_CASE(3, 2) ORNG_CASE(3, 3)
         ORNG_CASE(4, 0) ORNG_CASE(4, 1) ORNG_CASE(4, 2) ORNG_CASE(4, 3)
+        ORNG_CASE(5, 0) ORNG_CASE(5, 1) ORNG_CASE(5, 2) ORNG_CASE(5, 3)
+        ORNG_CASE(6, 0) ORNG_CASE(6, 1) ORNG_CASE(6, 2) ORNG_CASE(6, 3)
         default: break;
     }
 #undef ORNG_CASE

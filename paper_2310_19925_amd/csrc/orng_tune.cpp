@@ -53,6 +53,15 @@ static const uint32_t kDefaultTable[NGEN * NDIST][8] = {
         {64, 64, 0, 2, 512, 1, 1, 0},
         {256, 64, 0, 1, 128, 1, 1, 0},
         {128, 64, 0, 1, 512, 1, 1, 0},
+        // 13-round Threefry
+        {64, 8, 0, 1, 256, 8, 1, 0},
+        {512, 4, 8192, 1, 128, 16, 1, 0},
+        {512, 8, 8192, 1, 128, 16, 1, 0},
+        {512, 8, 8192, 1, 256, 16, 1, 0},
+        {256, 8, 0, 2, 256, 8, 1, 0},
+        {512, 8, 8192, 1, 128, 16, 1, 0},
+        {512, 4, 8192, 2, 128, 16, 1, 0},
+        {256, 8, 8192, 1, 256, 16, 1, 0},
 };
 
 static Tuned default_tuned(int gen, int dist) {

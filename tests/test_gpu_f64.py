@@ -37,7 +37,7 @@ def _case(R, O, gen, seed, ctr, off, n, pad=0):
     assert np.all(host[:pad] == -1) and np.all(host[pad + n:] == -1)
 
 
-@pytest.mark.parametrize("gen", range(5))
+@pytest.mark.parametrize("gen", range(7))
 def test_f64_fill_parity(R, O, gen):
     n = 3 * 8192 + 2 * 517 + 1
     _case(R, O, gen, 0x0123456789ABCDEF, 7, 0, n)
@@ -48,7 +48,7 @@ def test_f64_fill_parity(R, O, gen):
         _case(R, O, gen, 5, 6, off, n)
 
 
-@pytest.mark.parametrize("gen", range(5))
+@pytest.mark.parametrize("gen", range(7))
 def test_f64_fill_multi(R, O, gen):
     for n_streams, off, per in [(1000, 3, 5), (7, 1, 20001)]:
         out = torch.empty(n_streams * per, dtype=torch.int64, device="cuda")
@@ -63,7 +63,7 @@ def test_f64_bulk_sampled(R, O):
     n = 1 << 29
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     rng = np.random.default_rng(12)
-    for gen in range(5):
+    for gen in range(7):
         R.orng_fill(gen, F64, 0xFEED, 1, 0, n, out)
         torch.cuda.synchronize()
         js = np.unique(np.concatenate([[0, 1, n - 1], rng.integers(0, n, 200)]))
@@ -82,7 +82,7 @@ def _mixed_requests(rng, m, buf_words):
         k = 2 if dist == F64 else 1
         off_words += k - off_words % k  # 8-byte aligned doubles, 4-byte words
         off_words += int(rng.integers(0, 3)) * k
-        rows.append(dict(gen=int(rng.integers(0, 5)), dist=dist,
+        rows.append(dict(gen=int(rng.integers(0, 7)), dist=dist,
                          seed=int(rng.integers(0, 2**63)), ctr=int(rng.integers(0, 2**32)),
                          offset=int(rng.integers(0, 2**32 // k - n)), n=n, at=off_words))
         off_words += n * k

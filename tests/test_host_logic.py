@@ -87,7 +87,7 @@ def test_bd2_validation(L):
 
 
 def test_particle_streams_validation(L):
-    assert L.orng_particle_streams(5, 0, 10, 3, 0, 1, FAKE, None) == EINVAL
+    assert L.orng_particle_streams(7, 0, 10, 3, 0, 1, FAKE, None) == EINVAL
     assert L.orng_particle_streams(0, 0, 10, 0, 0, 1, FAKE, None) == EINVAL
     assert L.orng_particle_streams(0, 0, 10, 17, 0, 1, FAKE, None) == EINVAL
     assert L.orng_particle_streams(0, 0, 10, 3, 2**32 - 1, 2, FAKE, None) == ERANGE
@@ -117,7 +117,7 @@ def _reqs(rows):
 def test_batched_validation_rejects_whole_batch(L, fn):
     f = getattr(L, fn)
     cases = [
-        ([(0, 0, 0, 16, FAKE, 0), (5, 0, 0, 16, FAKE, 0)], EINVAL),     # bad generator
+        ([(0, 0, 0, 16, FAKE, 0), (7, 0, 0, 16, FAKE, 0)], EINVAL),     # bad generator
         ([(0, 4, 0, 16, FAKE, 0)], EINVAL),                              # bad distribution
         ([(0, 0, 0, 16, FAKE, 1)], EINVAL),                              # reserved flags
         ([(0, 0, 2**32 - 8, 16, FAKE, 0)], ERANGE),                      # past the period
@@ -179,7 +179,8 @@ def test_tune_table_loader(L, tmp_path):
     good = tmp_path / "good.txt"
     good.write_text("# header\n0 0 256 2 0 2 256 4 1 0\n4 1 256 64 0 2 256 1 1 0\n")
     assert L.orng_tune_load(str(good).encode()) == 0
-    assert L.orng_autotune(5, 0, None) == EINVAL
+    assert L.orng_autotune(7, 0, None) == EINVAL
+    assert L.orng_autotune(0, 4, None) == EINVAL
 
 
 def test_serve_create_validation(L):
