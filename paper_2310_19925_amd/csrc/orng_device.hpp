@@ -427,10 +427,11 @@ __device__ __forceinline__ void convert4(uint32_t w[4]) {
         w[0] = __float_as_uint(a); w[1] = __float_as_uint(b);
         w[2] = __float_as_uint(c); w[3] = __float_as_uint(d);
     } else if constexpr (D == D_F64U) {
-        const uint64_t a = (uint64_t)__double_as_longlong(u01_f64(w[0], w[1]));
-        const uint64_t b = (uint64_t)__double_as_longlong(u01_f64(w[2], w[3]));
-        w[0] = (uint32_t)a; w[1] = (uint32_t)(a >> 32);
-        w[2] = (uint32_t)b; w[3] = (uint32_t)(b >> 32);
+        // halves taken as 32-bit values (no 64-bit view of w, which kept the
+        // array out of registers)
+        const double a = u01_f64(w[0], w[1]), b = u01_f64(w[2], w[3]);
+        w[0] = (uint32_t)__double2loint(a); w[1] = (uint32_t)__double2hiint(a);
+        w[2] = (uint32_t)__double2loint(b); w[3] = (uint32_t)__double2hiint(b);
     }
 }
 

@@ -84,13 +84,19 @@ __device__ __forceinline__ void emit_block(SpanOut &o, uint64_t b, const uint32_
     }
     const bool prev_ok = lane > 0 || o.have_carry;
     const int64_t q0 = (int64_t)(b * 4) - d;  // first position of the chunk
+    // chunk word j (position q0 + j) comes from the previous block if j < d.
+    // The words are taken into scalars first and chosen by the uniform d:
+    // selecting array elements by a run-time index instead let the compiler
+    // keep the block in scratch memory when it holds split float64 values.
+    const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+    const uint32_t p1 = prev[1], p2 = prev[2], p3 = prev[3];
     uint32_t v[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        // chunk word j: position q0 + j; from the previous block if j < d
-        const uint32_t from_prev = d == 1 ? prev[3] : d == 2 ? prev[2 + (j & 1)] : prev[(1 + j) & 3];
-        const uint32_t from_own = d == 1 ? w[(j + 3) & 3] : d == 2 ? w[(j + 2) & 3] : w[(j + 1) & 3];
-        v[j] = j < d ? from_prev : from_own;
+    if (d == 1) {
+        v[0] = p3; v[1] = w0; v[2] = w1; v[3] = w2;
+    } else if (d == 2) {
+        v[0] = p2; v[1] = p3; v[2] = w0; v[3] = w1;
+    } else {
+        v[0] = p1; v[1] = p2; v[2] = p3; v[3] = w0;
     }
     if (prev_ok && q0 >= (int64_t)o.p0 && q0 + 4 <= (int64_t)o.pend) {
         store16<NT>(o.base + 4 * (q0 - (int64_t)o.p0), v);
