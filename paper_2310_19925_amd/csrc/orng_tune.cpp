@@ -37,9 +37,9 @@ static const uint32_t kDefaultTable[NGEN * NDIST][8] = {
         {64, 4, 0, 1, 512, 8, 1, 0},
         {512, 2, 8192, 1, 128, 16, 1, 0},
         {64, 4, 0, 2, 512, 8, 1, 0},
+        {256, 8, 8192, 1, 128, 16, 1, 0},
+        {512, 8, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 2, 128, 16, 1, 0},
-        {512, 8, 8192, 1, 128, 16, 1, 0},
-        {512, 8, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 1, 256, 16, 1, 0},
         {512, 4, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 1, 128, 16, 1, 0},
@@ -52,15 +52,15 @@ static const uint32_t kDefaultTable[NGEN * NDIST][8] = {
         {64, 64, 0, 2, 512, 1, 1, 0},
         {64, 64, 0, 2, 512, 1, 1, 0},
         {256, 64, 0, 1, 128, 1, 1, 0},
-        {128, 64, 0, 1, 512, 1, 1, 0},
+        {512, 64, 0, 2, 128, 1, 1, 8},
         // 13-round Threefry
         {64, 8, 0, 1, 256, 8, 1, 0},
         {512, 4, 8192, 1, 128, 16, 1, 0},
-        {512, 8, 8192, 1, 128, 16, 1, 0},
+        {512, 2, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 1, 256, 16, 1, 0},
         {256, 8, 0, 2, 256, 8, 1, 0},
         {512, 8, 8192, 1, 128, 16, 1, 0},
-        {512, 4, 8192, 2, 128, 16, 1, 0},
+        {256, 8, 0, 1, 256, 16, 1, 0},
         {256, 8, 8192, 1, 256, 16, 1, 0},
 };
 
