@@ -83,14 +83,16 @@ def roofs(gen, dist, n, ms):
 # calibration factors a 1 GiB device copy gives for each counter.  Valid only
 # for the kernel sources and launch table they were measured on: bench.py
 # reports null traffic when the hash of those sources differs.
-TRAFFIC_SRC_SHA = "692ccc0adbc58f5f"
-TRAFFIC_FACTORS = (1.9999251393683242, 1.0)  # FETCH, WRITE
+TRAFFIC_SRC_SHA = "b169ccc5402596e0"
+TRAFFIC_FACTORS = (1.9999241857658536, 1.0)  # FETCH, WRITE
 TRAFFIC_KIB = {
-    (0, 0): (63.1875, 4194304.0), (0, 1): (32.5, 4194563.125), (0, 2): (58.0625, 4194328.5), (0, 3): (34.0625, 4801733.875),
-    (1, 0): (37.3125, 4194304.0), (1, 1): (42.75, 4194329.875), (1, 2): (35.625, 4194304.5), (1, 3): (31.5, 4201499.875),
-    (2, 0): (34.5, 4194323.625), (2, 1): (35.5625, 4194333.0), (2, 2): (40.0, 4194304.0), (2, 3): (31.5, 4194336.0),
-    (3, 0): (32.0, 4194321.375), (3, 1): (32.0, 4194379.125), (3, 2): (79.4375, 4194330.125), (3, 3): (33.0, 4201655.875),
-    (4, 0): (39.9375, 4194304.0), (4, 1): (33.625, 4194304.0), (4, 2): (45.5625, 4194319.875), (4, 3): (30.875, 4203251.625),
+    (0, 0): (77.125, 4194304.0), (0, 1): (51.75, 4194586.875), (0, 2): (79.9375, 4194327.875), (0, 3): (44.0, 4194304.0),
+    (1, 0): (56.5, 4194325.5), (1, 1): (56.5, 4194304.125), (1, 2): (72.1875, 4194304.0), (1, 3): (49.5, 4194330.875),
+    (2, 0): (49.0, 4194326.5), (2, 1): (55.5, 4194312.875), (2, 2): (67.5, 4194304.0), (2, 3): (48.0, 4194306.375),
+    (3, 0): (52.0, 4194333.25), (3, 1): (52.5, 4194304.0), (3, 2): (101.8125, 4194325.25), (3, 3): (51.5, 4195830.25),
+    (4, 0): (37.125, 4194304.0), (4, 1): (33.6875, 4194304.0), (4, 2): (41.75, 4194353.125), (4, 3): (68.5625, 4194304.0),
+    (5, 0): (49.5, 4194849.75), (5, 1): (52.0, 4194355.25), (5, 2): (63.5, 4194304.0), (5, 3): (54.0, 4194867.25),
+    (6, 0): (53.0, 4194304.0), (6, 1): (55.0, 4197380.25), (6, 2): (59.5, 4194304.0), (6, 3): (50.0, 4195657.0),
 }
 
 
