@@ -78,6 +78,9 @@ def lib():
                                       i32]),
             "oracle_u01_f64": (C.c_double, [u32, u32]),
             "oracle_particle_streams": (i32, [i32, u64, u32, u32, u32, u32, vp, i32]),
+            "oracle_range_i32": (C.c_int32, [u32, u32, C.c_int32, C.c_int32]),
+            "oracle_fill_range": (i32, [i32, u64, u32, u32, u64, u64, C.c_int32, C.c_int32, vp,
+                                        i32]),
             "oracle_bd2": (i32, [u64, vp, u32, u32, u32, C.c_double, C.c_double, vp, vp, vp, vp,
                                  i32]),
         }
@@ -304,4 +307,20 @@ def particle_streams(gen, seed0, n_particles, draws, ctr0, n_iters, nthreads=Non
                                        out.ctypes.data, nthreads or default_threads())
     if rc != 0:
         raise ValueError("oracle_particle_streams rejected arguments (%d)" % rc)
+    return out
+
+
+def range_i32(w0, w1, lo, hi):
+    """Integer in [lo, hi) from the word pair (w0 at the even position)."""
+    return lib().oracle_range_i32(int(w0) & 0xFFFFFFFF, int(w1) & 0xFFFFFFFF, lo, hi)
+
+
+def fill_range(gen, seed, ctr0, n_streams, offset, per_stream, lo, hi, nthreads=None):
+    """(n_streams * per_stream) int32: integer sample offset + j of stream
+    (seed, ctr0 + i) at [i * per_stream + j]."""
+    out = np.empty(n_streams * per_stream, np.int32)
+    rc = lib().oracle_fill_range(gen, seed, ctr0, n_streams, offset, per_stream, lo, hi,
+                                 out.ctypes.data, nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_fill_range rejected arguments (%d)" % rc)
     return out

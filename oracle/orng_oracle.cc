@@ -699,4 +699,53 @@ int oracle_particle_streams(int gen, uint64_t seed0, uint32_t n_particles, uint3
     return 0;
 }
 
+/* ---------------------------------------------------------------------------
+ * Integers in [lo, hi) (reading of section 3, whose generators are meant to
+ * feed standard-library distributions; the paper defines no integer
+ * conversion).  Sample p takes the 64-bit integer x made of the words at
+ * positions 2p and 2p+1 (as the float64 uniform does) and scales it to the
+ * range by a full-width multiplication: lo + floor(x * r / 2^64), r = hi - lo.
+ * No remainder is taken: each of the r values has floor(2^64 / r) or
+ * ceil(2^64 / r) preimages among the 2^64 inputs, so its probability is within
+ * 2^-64 of 1/r (relative bias below r / 2^64 < 2^-32), where the remainder
+ * x mod r of one 32-bit word would favour low values by up to 2:1.  No
+ * rejection step either: it would consume a variable number of words and
+ * break the fixed sample-to-position map of the stream.  Pinned in the
+ * test-suite: power-of-two ranges against the top bits of the high word; the
+ * preimage thresholds ceil(v 2^64 / r) for random r and v in exact integer
+ * arithmetic; frequencies of a range where the remainder method would be
+ * off by 2:1.
+ * ------------------------------------------------------------------------- */
+int32_t oracle_range_i32(uint32_t w0, uint32_t w1, int32_t lo, int32_t hi) {
+    const uint64_t x = ((uint64_t)w1 << 32) | w0;
+    const uint64_t r = (uint64_t)((int64_t)hi - (int64_t)lo);
+    const unsigned __int128 prod = (unsigned __int128)x * r;
+    const uint64_t v = (uint64_t)(prod >> 64);
+    return (int32_t)((int64_t)lo + (int64_t)v);
+}
+
+int oracle_fill_range(int gen, uint64_t seed, uint32_t ctr0, uint32_t n_streams,
+                      uint64_t offset, uint64_t per_stream, int32_t lo, int32_t hi,
+                      int32_t *out, int nthreads) {
+    if (!valid_gen(gen) || lo >= hi) return -1;
+    const uint64_t lim = 1ull << 31;
+    if (offset > lim || per_stream > lim - offset) return -2;
+    if (n_streams && (uint64_t)ctr0 + n_streams - 1 > 0xFFFFFFFFull) return -2;
+    const uint64_t total = (uint64_t)n_streams * per_stream;
+    parallel_ranges(total, nthreads, [&](uint64_t a, uint64_t b, int) {
+        std::vector<uint32_t> w;
+        for (uint64_t j = a; j < b;) {
+            const uint64_t i = j / per_stream, q = j % per_stream;
+            uint64_t c = per_stream - q;
+            if (c > b - j) c = b - j;
+            if (c > PIECE) c = PIECE;
+            w.resize(2 * c);
+            words_range(gen, seed, ctr0 + (uint32_t)i, 2 * (offset + q), 2 * c, w.data());
+            for (uint64_t k = 0; k < c; ++k) out[j + k] = oracle_range_i32(w[2 * k], w[2 * k + 1], lo, hi);
+            j += c;
+        }
+    });
+    return 0;
+}
+
 } // extern "C"

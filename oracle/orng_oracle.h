@@ -115,6 +115,17 @@ int oracle_bd2(uint64_t pid0, const uint32_t *ids, uint32_t count, uint32_t step
 int oracle_particle_streams(int gen, uint64_t seed0, uint32_t n_particles, uint32_t draws,
                             uint32_t ctr0, uint32_t n_iters, uint32_t *out, int nthreads);
 
+/* --- integers in [lo, hi) (section 3: standard-distribution use) --------- */
+/* sample from two consecutive words of a stream (w0 at the even position):
+   lo + floor(x * (hi - lo) / 2^64) with x = (w1 << 32) | w0.  lo < hi. */
+int32_t oracle_range_i32(uint32_t w0, uint32_t w1, int32_t lo, int32_t hi);
+/* out[i*per_stream + j] = integer sample (offset + j) of stream (seed, ctr0 + i);
+   sample p is made from words 2p and 2p+1, so positions end at 2^31.
+   Returns 0, -1 (gen, or lo >= hi) or -2 (position or counter range). */
+int oracle_fill_range(int gen, uint64_t seed, uint32_t ctr0, uint32_t n_streams,
+                      uint64_t offset, uint64_t per_stream, int32_t lo, int32_t hi,
+                      int32_t *out, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif
