@@ -61,6 +61,10 @@ SLOTS_DIST = {0: 0.0, 1: 2.0, 2: 36.5 / 2}
 # exact fma and one scaling (float64 operations: one slot each at the
 # published 78.6 TFLOP/s vector rate); 8 bytes written per sample
 SLOTS_F64_CONVERT = 5
+# integer in [lo, hi): two words per sample, two 32x32->64 multiply-adds and
+# the add of lo; 4 bytes written per sample
+SLOTS_RANGE_CONVERT = 3
+RANGE_LO, RANGE_HI = -10**9, 10**9 + 7
 
 
 def roofs(gen, dist, n, ms):
@@ -69,6 +73,8 @@ def roofs(gen, dist, n, ms):
     t = ms * 1e-3
     if dist == 3:  # float64 uniform
         slots, nbytes = (2 * SLOTS_GEN[gen] + SLOTS_F64_CONVERT) * n, 8.0 * n
+    elif dist == "range":  # int32 in [lo, hi)
+        slots, nbytes = (2 * SLOTS_GEN[gen] + SLOTS_RANGE_CONVERT) * n, 4.0 * n
     else:
         slots, nbytes = (SLOTS_GEN[gen] + SLOTS_DIST[dist]) * n, 4.0 * n
     t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
@@ -502,6 +508,17 @@ def main():
             gbs = 4.0 * n / (ms * 1e-3) / 1e9
             extra.append({"gen": inputs.GEN_NAMES[g], "dist": inputs.DIST_NAMES[d],
                           "ms": round(ms, 4), "gsamples_s": round(ns / (ms * 1e-3) / 1e9, 2),
+                          "write_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                          "valu_frac": rf["valu_frac"], "binding": rf["binding"],
+                          "binding_frac": rf["binding_frac"]})
+        # integers in [lo, hi), 2^30 int32 samples each
+        for g in range(7):
+            ms = _time_events(stream, lambda: orng.orng_fill_range(
+                g, seed, 0, 1, 0, n, RANGE_LO, RANGE_HI, out, stream), 3)
+            rf = roofs(g, "range", n, ms)
+            gbs = 4.0 * n / (ms * 1e-3) / 1e9
+            extra.append({"gen": inputs.GEN_NAMES[g], "dist": "i32_range",
+                          "ms": round(ms, 4), "gsamples_s": round(n / (ms * 1e-3) / 1e9, 2),
                           "write_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                           "valu_frac": rf["valu_frac"], "binding": rf["binding"],
                           "binding_frac": rf["binding_frac"]})

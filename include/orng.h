@@ -125,6 +125,26 @@ int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particles, uint32_
                           uint32_t ctr0, uint32_t n_iters, void *d_out, void *stream);
 
 /*
+ * orng_fill_range -- integers in [lo, hi): d_out[i * per_stream + j] = sample
+ * (offset + j) of stream (seed, ctr0 + i), for i < n_streams, j < per_stream.
+ * The generators are meant to feed standard distributions (section 3); this is
+ * the integer one.  Sample p takes x = (w1 << 32) | w0 from the words w0, w1 at
+ * positions 2p and 2p+1 of the stream (the word pair of ORNG_F64_UNIFORM) and
+ * returns lo + floor(x * (hi - lo) / 2^64).  Every value's probability is
+ * within 2^-64 of 1 / (hi - lo): no remainder is taken (x mod r of one word
+ * favours low values by up to 2:1) and nothing is rejected, so each sample
+ * keeps its fixed positions and any range of samples can be made directly.
+ * Positions: offset + per_stream <= 2^31 samples per stream.
+ * d_out: device buffer of n_streams * per_stream int32 (caller-owned, 4-byte
+ *   aligned; 16-byte alignment of d_out + offset is the fast path).
+ * Errors: EINVAL (gen, lo >= hi, NULL or misaligned d_out with work to do),
+ *         ERANGE (offset + per_stream > 2^31, ctr0 + n_streams - 1 > 2^32 - 1).
+ *         n_streams = 0 or per_stream = 0 does nothing.
+ */
+int orng_fill_range(int gen, uint64_t seed, uint32_t ctr0, uint32_t n_streams, uint64_t offset,
+                    uint64_t per_stream, int32_t lo, int32_t hi, int32_t *d_out, void *stream);
+
+/*
  * orng_brownian -- fused overdamped Brownian walk (paper section 4, Fig. 1;
  * section 5.1), all steps in one launch.
  * Particle i (0 <= i < n_particles) owns the Philox4x32-10 stream

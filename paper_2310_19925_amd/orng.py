@@ -71,6 +71,7 @@ def _load():
         "orng_fill": [i32, i32, u64, u32, u64, u64, vp, vp],
         "orng_fill_multi": [i32, i32, u64, u32, u32, u64, u64, vp, vp],
         "orng_brownian": [u64, u32, u32, u32, u64, u32, f32, f32, vp, vp, u32, vp],
+        "orng_fill_range": [i32, u64, u32, u32, u64, u64, C.c_int32, C.c_int32, vp, vp],
         "orng_bd2": [u64, u32, u32, u32, C.c_double, C.c_double, vp, vp, vp, vp, u32, vp],
         "orng_particle_streams": [i32, u64, u32, u32, u32, u32, vp, vp],
         "orng_normal_pairs": [vp, vp, u64, vp, vp, vp],
@@ -138,6 +139,11 @@ def orng_fill(gen, dist, seed, ctr, offset, n, out, stream=None):
 def orng_fill_multi(gen, dist, seed, ctr0, n_streams, offset, per_stream, out, stream=None):
     _check(_lib.orng_fill_multi(gen, dist, seed, ctr0, n_streams, offset, per_stream, _ptr(out),
                                 _stream(stream)), "orng_fill_multi")
+
+
+def orng_fill_range(gen, seed, ctr0, n_streams, offset, per_stream, lo, hi, out, stream=None):
+    _check(_lib.orng_fill_range(gen, seed, ctr0, n_streams, offset, per_stream, lo, hi,
+                                _ptr(out), _stream(stream)), "orng_fill_range")
 
 
 def orng_brownian(seed, ctr0, n_particles, dim, step0, n_steps, dt, D, pos, msd=None,

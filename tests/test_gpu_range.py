@@ -1,0 +1,80 @@
+"""GPU parity of integer samples in [lo, hi) (orng_fill_range) against the
+oracle, bit for bit: every generator, ranges from one value to the whole
+int32 span, odd offsets, outputs off the 16- and 8-byte grid, ragged tails,
+the last samples of the stream, many streams, and 2^30 samples checked at
+sampled positions.  Cells around the output must stay untouched."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+I32_MIN, I32_MAX = -2**31, 2**31 - 1
+RANGES = [(0, 6), (-1000, 999), (I32_MIN, I32_MAX), (I32_MIN, 2**30), (5, 6), (0, 2**31 - 1)]
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_19925_amd import orng
+    return orng
+
+
+def _case(R, O, gen, seed, ctr, off, n, lo, hi, pad=0, n_streams=1):
+    print("case gen=%d seed=%d ctr=%d off=%d n=%d lo=%d hi=%d pad=%d streams=%d"
+          % (gen, seed, ctr, off, n, lo, hi, pad, n_streams), flush=True)
+    total = n * n_streams
+    buf = torch.full((total + pad + 3,), -7, dtype=torch.int32, device="cuda")
+    R.orng_fill_range(gen, seed, ctr, n_streams, off, n, lo, hi, buf[pad:pad + total])
+    torch.cuda.synchronize()
+    host = buf.cpu().numpy()
+    ref = O.fill_range(gen, seed, ctr, n_streams, off, n, lo, hi)
+    bad = np.nonzero(host[pad:pad + total] != ref)[0]
+    assert bad.size == 0, "first mismatch at %d of %d" % (bad[0], total)
+    assert np.all(host[:pad] == -7) and np.all(host[pad + total:] == -7)
+
+
+@pytest.mark.parametrize("gen", range(7))
+def test_range_fill_parity(R, O, gen):
+    n = 3 * 8192 + 2 * 517 + 1  # several Tyche tiles and counter groups, ragged tail
+    for k, (lo, hi) in enumerate(RANGES):
+        _case(R, O, gen, 0x0123456789ABCDEF + k, 7, k, n, lo, hi)
+    _case(R, O, gen, 42, 0, 5, n, -3, 3, pad=1)       # 4 bytes off the 8-byte grid
+    _case(R, O, gen, 42, 0, 6, n, -3, 3, pad=2)       # 8 bytes off the 16-byte grid
+    _case(R, O, gen, 42, 0, 2001, 9001, 0, 1000, pad=3)
+    for off, cnt in [(0, 1), (1, 1), (3, 2), (255, 3), (8191, 2), (2**31 - 1, 1),
+                     (2**31 - 8193, 8193)]:
+        _case(R, O, gen, 5, 6, off, cnt, -50, 50)
+
+
+@pytest.mark.parametrize("gen", range(7))
+def test_range_fill_multi(R, O, gen):
+    for n_streams, off, per in [(1000, 3, 5), (7, 1, 20001), (4, 0, 256)]:
+        _case(R, O, gen, 11, 100, off, per, -(2**20), 2**20, n_streams=n_streams)
+
+
+def test_range_bulk_sampled(R, O):
+    """2^30 samples (4 GiB) from one stream, checked on sampled positions."""
+    n = 1 << 30
+    lo, hi = -(10**9), 10**9 + 7
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    rng = np.random.default_rng(21)
+    for gen in range(7):
+        print("bulk gen=%d" % gen, flush=True)
+        R.orng_fill_range(gen, 0xFEED, 1, 1, 0, n, lo, hi, out)
+        torch.cuda.synchronize()
+        js = np.unique(np.concatenate([[0, 1, n - 1], rng.integers(0, n, 150)]))
+        got = out[torch.from_numpy(js).cuda()].cpu().numpy()
+        ref = np.array([O.fill_range(gen, 0xFEED, 1, 1, int(j), 1, lo, hi)[0] for j in js])
+        assert np.array_equal(got, ref), gen
+    del out
+    torch.cuda.empty_cache()
+
+
+def test_range_nothing_to_do(R):
+    R.orng_fill_range(0, 1, 2, 0, 0, 16, 0, 5, 0)
+    R.orng_fill_range(0, 1, 2, 1, 2**31, 0, 0, 5, 0)
+    with pytest.raises(R.OrngError):
+        R.orng_fill_range(0, 1, 2, 1, 0, 4, 5, 5, 0)

@@ -24,6 +24,7 @@ def L():
     lib.orng_normal_pairs.argtypes = [vp, vp, u64, vp, vp, vp]
     lib.orng_bd2.argtypes = [u64, u32, u32, u32, C.c_double, C.c_double, vp, vp, vp, vp, u32, vp]
     lib.orng_particle_streams.argtypes = [i32, u64, u32, u32, u32, u32, vp, vp]
+    lib.orng_fill_range.argtypes = [i32, u64, u32, u32, u64, u64, C.c_int32, C.c_int32, vp, vp]
     lib.orng_fill_batched.argtypes = [vp, C.c_size_t, vp]
     lib.orng_fill_each.argtypes = [vp, C.c_size_t, vp]
     lib.orng_tune_load.argtypes = [C.c_char_p]
@@ -196,3 +197,18 @@ def test_serve_create_validation(L):
                                C.byref(h)) == EINVAL
     assert L.orng_serve_create(C.cast(C.pointer(cfg_t(FAKE + 8, 1 << 20, 0, 0, 0)), C.c_void_p),
                                C.byref(h)) == EINVAL
+
+
+def test_fill_range_validation(L):
+    assert L.orng_fill_range(7, 0, 0, 1, 0, 4, 0, 10, FAKE, None) == EINVAL
+    assert L.orng_fill_range(-1, 0, 0, 1, 0, 4, 0, 10, FAKE, None) == EINVAL
+    assert L.orng_fill_range(0, 0, 0, 1, 0, 4, 10, 10, FAKE, None) == EINVAL
+    assert L.orng_fill_range(0, 0, 0, 1, 0, 4, 11, 10, FAKE, None) == EINVAL
+    assert L.orng_fill_range(0, 0, 0, 1, 2**31 - 3, 4, 0, 10, FAKE, None) == ERANGE
+    assert L.orng_fill_range(0, 0, 0, 1, 2**31 + 1, 0, 0, 10, FAKE, None) == ERANGE
+    assert L.orng_fill_range(0, 0, 2**32 - 2, 3, 0, 4, 0, 10, FAKE, None) == ERANGE
+    assert L.orng_fill_range(0, 0, 0, 1, 0, 4, 0, 10, None, None) == EINVAL
+    assert L.orng_fill_range(0, 0, 0, 1, 0, 4, 0, 10, FAKE + 2, None) == EINVAL
+    # nothing to do: no pointer is looked at
+    assert L.orng_fill_range(0, 0, 0, 0, 0, 4, 0, 10, None, None) == 0
+    assert L.orng_fill_range(0, 0, 0, 1, 2**31, 0, 0, 10, None, None) == 0
