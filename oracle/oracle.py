@@ -18,7 +18,7 @@ SRC = os.path.join(HERE, "orng_oracle.cc")
 LIB = os.path.join(HERE, "liborng_oracle.so")
 
 PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE, THREEFRY4X32_13, THREEFRY2X64_13 = range(7)
-U32, F32_UNIFORM, F32_NORMAL, F64_UNIFORM = range(4)
+U32, F32_UNIFORM, F32_NORMAL, F64_UNIFORM, F64_NORMAL = range(5)
 GENS = (PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE)
 DISTS = (U32, F32_UNIFORM, F32_NORMAL)  # the float32/u32 set; F64_UNIFORM is separate
 
@@ -78,6 +78,11 @@ def lib():
                                       i32]),
             "oracle_u01_f64": (C.c_double, [u32, u32]),
             "oracle_particle_streams": (i32, [i32, u64, u32, u32, u32, u32, vp, i32]),
+            "oracle_ln_u1_f64": (C.c_double, [u64]),
+            "oracle_sincos_turn_f64": (None, [u64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+            "oracle_normal_pair_f64": (None, [u32, u32, u32, u32, C.POINTER(C.c_double)]),
+            "oracle_ln_u1_f64_n": (None, [vp, u64, vp]),
+            "oracle_sincos_turn_f64_n": (None, [vp, u64, vp, vp]),
             "oracle_range_i32": (C.c_int32, [u32, u32, C.c_int32, C.c_int32]),
             "oracle_fill_range": (i32, [i32, u64, u32, u32, u64, u64, C.c_int32, C.c_int32, vp,
                                         i32]),
@@ -217,7 +222,7 @@ def normal_pair_n(x0, x1):
 
 
 def _dtype(dist):
-    return {U32: np.uint32, F64_UNIFORM: np.float64}.get(dist, np.float32)
+    return {U32: np.uint32, F64_UNIFORM: np.float64, F64_NORMAL: np.float64}.get(dist, np.float32)
 
 
 def fill(gen, dist, seed, ctr, offset, n, nthreads=None):
@@ -324,3 +329,34 @@ def fill_range(gen, seed, ctr0, n_streams, offset, per_stream, lo, hi, nthreads=
     if rc != 0:
         raise ValueError("oracle_fill_range rejected arguments (%d)" % rc)
     return out
+
+
+def ln_u1_f64(K):
+    return lib().oracle_ln_u1_f64(int(K))
+
+
+def sincos_turn_f64(k):
+    c, s = C.c_double(), C.c_double()
+    lib().oracle_sincos_turn_f64(int(k), C.byref(c), C.byref(s))
+    return c.value, s.value
+
+
+def normal_pair_f64(w0, w1, w2, w3):
+    out = (C.c_double * 2)()
+    lib().oracle_normal_pair_f64(*(int(w) & 0xFFFFFFFF for w in (w0, w1, w2, w3)), out)
+    return out[0], out[1]
+
+
+def ln_u1_f64_n(K):
+    K = np.ascontiguousarray(K, dtype=np.uint64)
+    out = np.empty(K.shape, np.float64)
+    lib().oracle_ln_u1_f64_n(K.ctypes.data, K.size, out.ctypes.data)
+    return out
+
+
+def sincos_turn_f64_n(k):
+    k = np.ascontiguousarray(k, dtype=np.uint64)
+    c = np.empty(k.shape, np.float64)
+    s = np.empty(k.shape, np.float64)
+    lib().oracle_sincos_turn_f64_n(k.ctypes.data, k.size, c.ctypes.data, s.ctypes.data)
+    return c, s

@@ -202,6 +202,22 @@ void samples_range(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t p0, 
         for (uint64_t j = 0; j < count; ++j) o[j] = oracle_u01_f64(w[2 * j], w[2 * j + 1]);
         return;
     }
+    if (dist == OR_F64_NORMAL) {
+        /* sample p is member (p mod 2) of pair p/2, which is built from the
+           four words 4*(p/2) .. 4*(p/2)+3 */
+        const uint64_t m0 = p0 / 2, m1 = (p0 + count - 1) / 2;
+        std::vector<uint32_t> w(4 * (m1 - m0 + 1));
+        words_range(gen, seed, ctr, 4 * m0, w.size(), w.data());
+        double *o = (double *)dst;
+        for (uint64_t j = 0; j < count; ++j) {
+            const uint64_t p = p0 + j, m = p / 2;
+            const uint32_t *q = &w[4 * (m - m0)];
+            double pair[2];
+            oracle_normal_pair_f64(q[0], q[1], q[2], q[3], pair);
+            o[j] = pair[p & 1];
+        }
+        return;
+    }
     /* normal: sample p is member (p mod 2) of pair p/2, which is built from
        words 2*(p/2) and 2*(p/2)+1 */
     const uint64_t m0 = p0 / 2, m1 = (p0 + count - 1) / 2;
@@ -217,10 +233,11 @@ void samples_range(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t p0, 
 }
 
 bool valid_gen(int g) { return g >= OR_PHILOX && g <= OR_THREEFRY2X64_13; }
-bool valid_dist(int d) { return d >= OR_U32 && d <= OR_F64_UNIFORM; }
+bool valid_dist(int d) { return d >= OR_U32 && d <= OR_F64_NORMAL; }
 /* bytes per sample, and stream positions (words) per sample */
-uint64_t sample_bytes(int dist) { return dist == OR_F64_UNIFORM ? 8 : 4; }
-uint64_t sample_limit(int dist) { return dist == OR_F64_UNIFORM ? (1ull << 31) : (1ull << 32); }
+bool is_f64(int dist) { return dist == OR_F64_UNIFORM || dist == OR_F64_NORMAL; }
+uint64_t sample_bytes(int dist) { return is_f64(dist) ? 8 : 4; }
+uint64_t sample_limit(int dist) { return is_f64(dist) ? (1ull << 31) : (1ull << 32); }
 
 template <class F>
 void parallel_ranges(uint64_t n, int nthreads, F body) {
@@ -382,6 +399,15 @@ void oracle_sample(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t p, v
             const double d = oracle_u01_f64(oracle_word(gen, seed, ctr, 2 * p),
                                             oracle_word(gen, seed, ctr, 2 * p + 1));
             std::memcpy(out, &d, 8);
+            return;
+        }
+        if (dist == OR_F64_NORMAL) {
+            const uint64_t m = p / 2;
+            double pair[2];
+            oracle_normal_pair_f64(oracle_word(gen, seed, ctr, 4 * m), oracle_word(gen, seed, ctr, 4 * m + 1),
+                                   oracle_word(gen, seed, ctr, 4 * m + 2), oracle_word(gen, seed, ctr, 4 * m + 3),
+                                   pair);
+            std::memcpy(out, &pair[p & 1], 8);
             return;
         }
         uint64_t m = p / 2;
@@ -621,6 +647,115 @@ int oracle_brownian(uint64_t seed, uint32_t ctr0, const uint32_t *ids, uint32_t 
 double oracle_u01_f64(uint32_t w0, uint32_t w1) {
     const uint64_t x = ((uint64_t)w1 << 32) | w0;
     return (double)(x >> 11) * 0x1p-53;
+}
+
+/* ---------------------------------------------------------------------------
+ * float64 Box-Muller normals (reading: the paper's generators feed standard
+ * distributions, section 3, and it names no conversion).  Pair m (samples 2m
+ * and 2m+1) is made from the four words 4m..4m+3: x = (w1 << 32) | w0 and
+ * y = (w3 << 32) | w2 give u1 = ((x >> 11) + 1) 2^-53 in (0, 1] and
+ * u2 = (y >> 11) 2^-53 in [0, 1); R = sqrt(-2 ln u1), z0 = R cos 2 pi u2,
+ * z1 = R sin 2 pi u2 (Box and Muller, Ann. Math. Stat. 1958).  ln, cos and
+ * sin are this library's own float64 functions below, so a result is a fixed
+ * sequence of IEEE float64 operations, each rounded once (every Horner step
+ * is one fused multiply-add; division and square root correctly rounded).
+ *
+ * ln u1, u1 = K 2^-53: K = m 2^e with m in [sqrt(1/2), sqrt(2)) split off in
+ * integers (bit length of K; m is exact); ln m = 2 atanh(s), s = (m-1)/(m+1),
+ * by its series through s^21 (|s| <= 0.1716, first omitted term below
+ * 2^-60 relative); ln u1 = (e - 53) ln2_hi + ((e - 53) ln2_lo + ln m), ln2_hi
+ * holding ln 2's leading 40 bits, so the first product is exact.
+ * cos and sin of 2 pi k 2^-53: the nearest quarter turn j is taken off k in
+ * integers, leaving a fraction f of at most 1/8 turn, exact; x = f * 2pi
+ * (one rounding), |x| <= pi/4; Taylor series of sin through x^19 and of cos
+ * through x^18 (first omitted terms below 2^-65), then the quarter-turn
+ * rotation, which is exact.
+ * Pinned in the test-suite: against 40-digit decimal arithmetic (its own
+ * series for ln, pi, sin, cos) within stated ulp bounds on edge and random
+ * arguments over every binade; exact values at quarter turns and at u1 = 1;
+ * moments and Kolmogorov-Smirnov of many samples.
+ * ------------------------------------------------------------------------- */
+static const double LN2_HI = 0x1.62e42fefa2p-1;         /* ln 2 truncated to 40 bits */
+static const double LN2_LO = 0x1.9ef35793c7673p-41;     /* ln 2 - LN2_HI, rounded */
+static const double SQRT2 = 0x1.6a09e667f3bcdp+0;       /* sqrt 2, rounded */
+static const double TWO_PI = 0x1.921fb54442d18p+2;      /* 2 pi, rounded */
+
+double oracle_ln_u1_f64(uint64_t K) {
+    int e = 63 - __builtin_clzll(K);                     /* 2^e <= K < 2^(e+1) */
+    double m = std::ldexp((double)K, -e);                /* [1, 2), exact */
+    if (m >= SQRT2) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double P = 1.0 / 21.0;                               /* sum of z^k / (2k+1), k >= 1, over z */
+    P = std::fma(P, z, 1.0 / 19.0);
+    P = std::fma(P, z, 1.0 / 17.0);
+    P = std::fma(P, z, 1.0 / 15.0);
+    P = std::fma(P, z, 1.0 / 13.0);
+    P = std::fma(P, z, 1.0 / 11.0);
+    P = std::fma(P, z, 1.0 / 9.0);
+    P = std::fma(P, z, 1.0 / 7.0);
+    P = std::fma(P, z, 1.0 / 5.0);
+    P = std::fma(P, z, 1.0 / 3.0);
+    const double t = 2.0 * s;
+    const double ln_m = std::fma(t, z * P, t);           /* 2s (1 + z P) */
+    const double E = (double)(e - 53);
+    return std::fma(E, LN2_HI, std::fma(E, LN2_LO, ln_m));
+}
+
+void oracle_sincos_turn_f64(uint64_t k, double *c, double *s) {
+    const uint64_t j = (k + (1ull << 50)) >> 51;         /* nearest quarter turn, 0..4 */
+    const int64_t r = (int64_t)k - (int64_t)(j << 51);   /* [-2^50, 2^50] */
+    const double f = (double)r * 0x1p-53;                /* turns, exact */
+    const double x = f * TWO_PI;
+    const double z = x * x;
+    double S = -1.0 / 121645100408832000.0;              /* -1/19! */
+    S = std::fma(S, z, 1.0 / 355687428096000.0);         /*  1/17! */
+    S = std::fma(S, z, -1.0 / 1307674368000.0);          /* -1/15! */
+    S = std::fma(S, z, 1.0 / 6227020800.0);              /*  1/13! */
+    S = std::fma(S, z, -1.0 / 39916800.0);               /* -1/11! */
+    S = std::fma(S, z, 1.0 / 362880.0);                  /*  1/9!  */
+    S = std::fma(S, z, -1.0 / 5040.0);                   /* -1/7!  */
+    S = std::fma(S, z, 1.0 / 120.0);                     /*  1/5!  */
+    S = std::fma(S, z, -1.0 / 6.0);                      /* -1/3!  */
+    const double sn = std::fma(x * z, S, x);
+    double Cp = 1.0 / 6402373705728000.0;                /*  1/18! */
+    Cp = std::fma(Cp, z, -1.0 / 20922789888000.0);       /* -1/16! */
+    Cp = std::fma(Cp, z, 1.0 / 87178291200.0);           /*  1/14! */
+    Cp = std::fma(Cp, z, -1.0 / 479001600.0);            /* -1/12! */
+    Cp = std::fma(Cp, z, 1.0 / 3628800.0);               /*  1/10! */
+    Cp = std::fma(Cp, z, -1.0 / 40320.0);                /* -1/8!  */
+    Cp = std::fma(Cp, z, 1.0 / 720.0);                   /*  1/6!  */
+    Cp = std::fma(Cp, z, -1.0 / 24.0);                   /* -1/4!  */
+    Cp = std::fma(Cp, z, 1.0 / 2.0);                     /*  1/2!, sign below */
+    const double cs = std::fma(-z, Cp, 1.0);
+    switch (j & 3) {
+    case 0: *c = cs; *s = sn; break;
+    case 1: *c = -sn; *s = cs; break;
+    case 2: *c = -cs; *s = -sn; break;
+    default: *c = sn; *s = -cs; break;
+    }
+}
+
+void oracle_normal_pair_f64(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, double out[2]) {
+    const uint64_t x = ((uint64_t)w1 << 32) | w0;
+    const uint64_t y = ((uint64_t)w3 << 32) | w2;
+    const double ln = oracle_ln_u1_f64((x >> 11) + 1);
+    const double R = std::sqrt(std::fma(-2.0, ln, 0.0)); /* -2 ln exactly; u1 = 1 gives +0 */
+    double c, s;
+    oracle_sincos_turn_f64(y >> 11, &c, &s);
+    out[0] = R * c;
+    out[1] = R * s;
+}
+
+void oracle_ln_u1_f64_n(const uint64_t *K, uint64_t n, double *out) {
+    for (uint64_t i = 0; i < n; ++i) out[i] = oracle_ln_u1_f64(K[i]);
+}
+
+void oracle_sincos_turn_f64_n(const uint64_t *k, uint64_t n, double *c, double *s) {
+    for (uint64_t i = 0; i < n; ++i) oracle_sincos_turn_f64(k[i], &c[i], &s[i]);
 }
 
 /* ---------------------------------------------------------------------------

@@ -42,7 +42,7 @@ extern "C" {
    numbers are part of the interface, not shared code) */
 enum { OR_PHILOX = 0, OR_THREEFRY4X32 = 1, OR_THREEFRY2X64 = 2, OR_SQUARES = 3, OR_TYCHE = 4,
        OR_THREEFRY4X32_13 = 5, OR_THREEFRY2X64_13 = 6 };
-enum { OR_U32 = 0, OR_F32_UNIFORM = 1, OR_F32_NORMAL = 2, OR_F64_UNIFORM = 3 };
+enum { OR_U32 = 0, OR_F32_UNIFORM = 1, OR_F32_NORMAL = 2, OR_F64_UNIFORM = 3, OR_F64_NORMAL = 4 };
 
 /* --- raw generator cores ------------------------------------------------ */
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -60,8 +60,8 @@ uint32_t oracle_tyche_next(uint32_t st[4]);        /* one MIX, returns b */
 /* word at position p of stream (seed, ctr) of generator gen */
 uint32_t oracle_word(int gen, uint64_t seed, uint32_t ctr, uint64_t p);
 /* sample at position p of the given distribution; writes 4 bytes to *out
-   (8 for OR_F64_UNIFORM, whose sample p is made from words 2p and 2p+1, so
-   its positions end at 2^31) */
+   (8 for OR_F64_UNIFORM and OR_F64_NORMAL, whose sample p is made from words
+   2p and 2p+1, so their positions end at 2^31) */
 void oracle_sample(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t p, void *out);
 
 /* --- float32 conversions --------------------------------------------------- */
@@ -114,6 +114,13 @@ int oracle_bd2(uint64_t pid0, const uint32_t *ids, uint32_t count, uint32_t step
    seed range overflows). */
 int oracle_particle_streams(int gen, uint64_t seed0, uint32_t n_particles, uint32_t draws,
                             uint32_t ctr0, uint32_t n_iters, uint32_t *out, int nthreads);
+
+/* --- float64 Box-Muller normals (see orng_oracle.cc) --------------------- */
+double oracle_ln_u1_f64(uint64_t K);               /* ln(K 2^-53), K in [1, 2^53] */
+void oracle_sincos_turn_f64(uint64_t k, double *c, double *s); /* of 2 pi k 2^-53, k < 2^53 */
+void oracle_normal_pair_f64(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, double out[2]);
+void oracle_ln_u1_f64_n(const uint64_t *K, uint64_t n, double *out);
+void oracle_sincos_turn_f64_n(const uint64_t *k, uint64_t n, double *c, double *s);
 
 /* --- integers in [lo, hi) (section 3: standard-distribution use) --------- */
 /* sample from two consecutive words of a stream (w0 at the even position):
