@@ -61,6 +61,12 @@ SLOTS_DIST = {0: 0.0, 1: 2.0, 2: 36.5 / 2}
 # exact fma and one scaling (float64 operations: one slot each at the
 # published 78.6 TFLOP/s vector rate); 8 bytes written per sample
 SLOTS_F64_CONVERT = 5
+# float64 normal, per pair (two samples) counted from the definition, one slot
+# per float64 operation (full rate: 78.6 TFLOP/s = one FMA per lane and clock):
+# ln 35 (exponent split 5, division 11, series 11, assembly 8), square root 13,
+# sin/cos 40 (integer quarter-turn split 10, series 22, rotation 8), products 2,
+# word handling 6; 8 bytes written per sample
+SLOTS_F64N_CONVERT = 96 / 2
 # integer in [lo, hi): two words per sample, two 32x32->64 multiply-adds and
 # the add of lo; 4 bytes written per sample
 SLOTS_RANGE_CONVERT = 3
@@ -73,6 +79,8 @@ def roofs(gen, dist, n, ms):
     t = ms * 1e-3
     if dist == 3:  # float64 uniform
         slots, nbytes = (2 * SLOTS_GEN[gen] + SLOTS_F64_CONVERT) * n, 8.0 * n
+    elif dist == 4:  # float64 normal
+        slots, nbytes = (2 * SLOTS_GEN[gen] + SLOTS_F64N_CONVERT) * n, 8.0 * n
     elif dist == "range":  # int32 in [lo, hi)
         slots, nbytes = (2 * SLOTS_GEN[gen] + SLOTS_RANGE_CONVERT) * n, 4.0 * n
     else:
@@ -495,14 +503,15 @@ def main():
                         "store_ceiling_frac": round(gbs / ceiling_gbs, 4),
                         "valu_tslots_s": rf["valu_tslots_s"], "valu_frac": rf["valu_frac"],
                         "binding": rf["binding"], "binding_frac": rf["binding_frac"]})
-    # float64 uniform fills (4 GiB each), measured beside the step: not part of
-    # the configured workload, so not in `value`;
+    # float64 uniform and normal fills (4 GiB each), measured beside the step:
+    # not part of the configured workload, so not in `value`;
     # and the 13-round Threefry variants (4 GiB each)
     extra = []
     if not args.only:
-        cases = [(g, 3) for g in range(7)] + [(g, d) for g in (5, 6) for d in range(3)]
+        cases = [(g, 3) for g in range(7)] + [(g, 4) for g in range(7)] + \
+            [(g, d) for g in (5, 6) for d in range(3)]
         for g, d in cases:
-            ns = n // 2 if d == 3 else n
+            ns = n // 2 if d in (3, 4) else n
             ms = _time_events(stream, lambda: orng.orng_fill(g, d, seed, 0, 0, ns, out, stream), 3)
             rf = roofs(g, d, ns, ms)
             gbs = 4.0 * n / (ms * 1e-3) / 1e9

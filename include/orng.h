@@ -47,12 +47,13 @@ enum {
     ORNG_THREEFRY2X64_13 = 6
 };
 
-/* distributions; samples are 4 bytes, 8 for ORNG_F64_UNIFORM */
+/* distributions; samples are 4 bytes, 8 for the two float64 ones */
 enum {
     ORNG_U32 = 0,         /* raw 32-bit word */
     ORNG_F32_UNIFORM = 1, /* (word >> 8) * 2^-24, in [0, 1) */
     ORNG_F32_NORMAL = 2,  /* Box-Muller, one member of a pair per sample */
-    ORNG_F64_UNIFORM = 3  /* two words per sample: ((w1 << 32 | w0) >> 11) * 2^-53, in [0, 1) */
+    ORNG_F64_UNIFORM = 3, /* two words per sample: ((w1 << 32 | w0) >> 11) * 2^-53, in [0, 1) */
+    ORNG_F64_NORMAL = 4   /* float64 Box-Muller, pair m from the four words 4m..4m+3 */
 };
 
 /* status codes */
@@ -75,7 +76,13 @@ enum {
  * words 2p (w0) and 2p+1 (w1), so its samples end at 2^31 (the float64 draw
  * of the paper's example, section 4 Fig. 1); for F32_NORMAL, sample p is
  * member p mod 2 of the Box-Muller pair built from words 2*(p/2) and
- * 2*(p/2)+1.  The stream's words are:
+ * 2*(p/2)+1.  For F64_NORMAL, sample p is member p mod 2 of the pair built
+ * from words 4*(p/2) .. 4*(p/2)+3: x = (w1 << 32) | w0, y = (w3 << 32) | w2,
+ * u1 = ((x >> 11) + 1) 2^-53, u2 = (y >> 11) 2^-53, R = sqrt(-2 ln u1),
+ * (R cos 2 pi u2, R sin 2 pi u2), with the library's own float64 ln, cos and
+ * sin (each within 2 ulp; results are reproducible bit for bit).  Both float64
+ * distributions use two words per sample, so their samples end at 2^31.
+ * The stream's words are:
  *   Philox4x32-10  : word p = word p%4 of Philox(counter (p/4, ctr, 0, 0),
  *                    key (lo32 seed, hi32 seed))
  *   Threefry4x32-20: same counter, key (lo32 seed, hi32 seed, 0, 0)
@@ -90,9 +97,10 @@ enum {
  *                    instance seeded with (seed, ctr) whose c word is XORed
  *                    with t*64 + (r/4)%64.
  * Arguments: gen, dist (enums above); d_out: device buffer of n samples
- * (n * 4 bytes, 4-byte aligned; n * 8 bytes, 8-byte aligned for F64_UNIFORM).
+ * (n * 4 bytes, 4-byte aligned; n * 8 bytes, 8-byte aligned for the float64
+ * distributions).
  * Errors: EINVAL (enum, NULL, alignment), ERANGE (offset + n past the last
- *         sample: 2^32, or 2^31 for F64_UNIFORM).
+ *         sample: 2^32, or 2^31 for the float64 distributions).
  */
 int orng_fill(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t offset, uint64_t n,
               void *d_out, void *stream);

@@ -69,7 +69,7 @@ __device__ __forceinline__ uint64_t bcast_lane0(uint64_t x) {
 }
 
 // Generate spans j0, j0 + step, ... < W of tile t of the batch (wave-uniform).
-template <bool NT>
+template <bool NT, bool F64N>
 __device__ __forceinline__ void run_tile(const DevReq *reqs, const uint32_t *map, uint64_t t,
                                          uint32_t W, uint32_t j0, uint32_t step, uint32_t lane) {
     const uint32_t r = map[t];
@@ -78,11 +78,11 @@ __device__ __forceinline__ void run_tile(const DevReq *reqs, const uint32_t *map
     const int gen = (int)(q.flags & 15u), dist = (int)((q.flags >> 4) & 15u);
     const uint64_t span0 = q.first_span + (t - q.tile_start) * W;
     for (uint32_t j = j0; j < W; j += step)
-        process_span_any<NT>(gen, dist, ks, q.ctr, q.out, q.p0, q.p0 + q.n, span0 + j, q.unroll,
-                             (q.flags >> 8) & 3u, lane);
+        process_span_any<NT, F64N>(gen, dist, ks, q.ctr, q.out, q.p0, q.p0 + q.n, span0 + j,
+                                   q.unroll, (q.flags >> 8) & 3u, lane);
 }
 
-template <bool NT>
+template <bool NT, bool F64N>
 __global__ __launch_bounds__(512) void k_batched(BatchView v) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t total = v.hdr->total_tiles;
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(512) void k_batched(BatchView v) {
         t0 = bcast_lane0(t0);
         if (t0 >= total) break;
         const uint64_t t1 = t0 + chunk < total ? t0 + chunk : total;
-        for (uint64_t t = t0; t < t1; ++t) run_tile<NT>(v.reqs, v.map, t, W, 0, 1, lane);
+        for (uint64_t t = t0; t < t1; ++t) run_tile<NT, F64N>(v.reqs, v.map, t, W, 0, 1, lane);
     }
 }
 
@@ -105,13 +105,13 @@ __global__ __launch_bounds__(512) void k_batched(BatchView v) {
 // count) so that a captured graph serves many batch sizes; workgroups past the
 // last tile exit at once.  Each XCD takes a contiguous range of tiles, so the
 // tile map and request rows it reads stay in its own L2.
-template <bool NT>
+template <bool NT, bool F64N>
 __global__ __launch_bounds__(512) void k_batched_static(BatchView v) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t t = xcd_tile(blockIdx.x, gridDim.x);
     if (t >= v.hdr->total_tiles) return;
     const uint32_t j = wave_uniform(threadIdx.x >> 6);
-    run_tile<NT>(v.reqs, v.map, t, blockDim.x >> 6, j, 0xFFFFu, lane);
+    run_tile<NT, F64N>(v.reqs, v.map, t, blockDim.x >> 6, j, 0xFFFFu, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -213,16 +213,22 @@ static BatchShape batch_shape(int gen, int dist, uint64_t tiles) {
     return s;
 }
 
-static void *batched_kernel(const BatchShape &s) {
+template <bool F64N>
+static void *batched_kernel_v(const BatchShape &s) {
     if (s.persistent)
-        return s.nt ? reinterpret_cast<void *>(&k_batched<true>)
-                    : reinterpret_cast<void *>(&k_batched<false>);
-    return s.nt ? reinterpret_cast<void *>(&k_batched_static<true>)
-                : reinterpret_cast<void *>(&k_batched_static<false>);
+        return s.nt ? reinterpret_cast<void *>(&k_batched<true, F64N>)
+                    : reinterpret_cast<void *>(&k_batched<false, F64N>);
+    return s.nt ? reinterpret_cast<void *>(&k_batched_static<true, F64N>)
+                : reinterpret_cast<void *>(&k_batched_static<false, F64N>);
+}
+
+// The variant with the float64 normal cases only for batches that hold one.
+static void *batched_kernel(const BatchShape &s, bool f64n) {
+    return f64n ? batched_kernel_v<true>(s) : batched_kernel_v<false>(s);
 }
 
 int validate_request(const orng_req_t &r) {
-    if (r.gen > ORNG_THREEFRY2X64_13 || r.dist > ORNG_F64_UNIFORM || r.flags != 0) return ORNG_EINVAL;
+    if (r.gen > ORNG_THREEFRY2X64_13 || r.dist > ORNG_F64_NORMAL || r.flags != 0) return ORNG_EINVAL;
     const uint64_t k = words_per_sample((int)r.dist), lim = sample_limit((int)r.dist);
     if (r.offset > lim || r.n > lim - r.offset) return ORNG_ERANGE;
     if (r.n == 0) return ORNG_OK;
@@ -337,6 +343,7 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     std::vector<uint64_t> range_tiles(rg.T + 1, 0);
     std::vector<size_t> range_bad(rg.T, nreq);  // first invalid request of each range
     std::vector<int> range_st(rg.T, ORNG_OK);
+    std::vector<char> range_f64n(rg.T, 0);  // a float64 normal request with work
     uint32_t unroll_of[NGEN][NDIST];  // one table lookup per pair, not per request
     for (int g = 0; g < NGEN; ++g)
         for (int d = 0; d < NDIST; ++d)
@@ -359,6 +366,7 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
             unr[i] = 0;
             if (!reqs[i].n) continue;
             unr[i] = unroll_of[reqs[i].gen][reqs[i].dist];
+            if (reqs[i].dist == ORNG_F64_NORMAL) range_f64n[t] = 1;
             request_tiles(reqs[i], unr[i], W, &fspan[i], &cnt[i]);
             sum += cnt[i];
         }
@@ -367,6 +375,8 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     for (size_t t = 0; t < rg.T; ++t)
         if (range_bad[t] < nreq) return range_st[t];  // ranges are in list order
     for (size_t t = 0; t < rg.T; ++t) range_tiles[t + 1] += range_tiles[t];
+    bool f64n = false;
+    for (size_t t = 0; t < rg.T; ++t) f64n = f64n || range_f64n[t];
     const uint64_t tiles = range_tiles[rg.T];
     if (tiles == 0) return ORNG_OK;
     if (tiles > (1ull << 28)) return ORNG_ENOMEM;
@@ -431,13 +441,14 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     void *args[] = {&v};
     if (use_graphs()) {
         const uint64_t key[4] = {reinterpret_cast<uintptr_t>(c.d_buf), sh.wg, sh.grid,
-                                 (uint64_t)sh.nt | ((uint64_t)sh.persistent << 1)};
+                                 (uint64_t)sh.nt | ((uint64_t)sh.persistent << 1) |
+                                     ((uint64_t)f64n << 2)};
         if (!c.exec || std::memcmp(key, c.graph_key, sizeof key) != 0) {
             if (c.exec) { hipGraphExecDestroy(c.exec); c.exec = nullptr; }
             if (c.graph) { hipGraphDestroy(c.graph); c.graph = nullptr; }
             ORNG_TRY(hipStreamBeginCapture(db->capture, hipStreamCaptureModeThreadLocal));
-            hipError_t le = hipLaunchKernel(batched_kernel(sh), dim3(sh.grid), dim3(sh.wg),
-                                            args, 0, db->capture);
+            hipError_t le = hipLaunchKernel(batched_kernel(sh, f64n), dim3(sh.grid),
+                                            dim3(sh.wg), args, 0, db->capture);
             hipError_t ce = hipStreamEndCapture(db->capture, &c.graph);
             ORNG_TRY(le);
             ORNG_TRY(ce);
@@ -446,7 +457,7 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
         }
         ORNG_TRY(hipGraphLaunch(c.exec, stream));
     } else {
-        ORNG_TRY(hipLaunchKernel(batched_kernel(sh), dim3(sh.grid), dim3(sh.wg), args, 0,
+        ORNG_TRY(hipLaunchKernel(batched_kernel(sh, f64n), dim3(sh.grid), dim3(sh.wg), args, 0,
                                  stream));
     }
     ORNG_TRY(hipEventRecord(c.done, stream));

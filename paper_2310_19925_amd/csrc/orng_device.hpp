@@ -24,8 +24,8 @@ namespace orng {
 
 enum GenId : int { G_PHILOX = 0, G_TF4X32 = 1, G_TF2X64 = 2, G_SQUARES = 3, G_TYCHE = 4,
                    G_TF4X32_13 = 5, G_TF2X64_13 = 6 };
-enum DistId : int { D_U32 = 0, D_UNIFORM = 1, D_NORMAL = 2, D_F64U = 3 };
-constexpr int NGEN = 7, NDIST = 4;
+enum DistId : int { D_U32 = 0, D_UNIFORM = 1, D_NORMAL = 2, D_F64U = 3, D_F64N = 4 };
+constexpr int NGEN = 7, NDIST = 5;
 
 // Per-launch key material, uniform across the grid.
 struct KeySched {
@@ -412,9 +412,101 @@ __device__ __forceinline__ double u01_f64(uint32_t w0, uint32_t w1) {
     return fma((double)w1, 0x1p21, (double)(w0 >> 11)) * 0x1p-53;
 }
 
+// ---------------------------------------------------------------------------
+// float64 Box-Muller pair from the four words of a block: x = (w1 << 32) | w0,
+// y = (w3 << 32) | w2, u1 = ((x >> 11) + 1) 2^-53 in (0, 1], u2 = (y >> 11)
+// 2^-53; z0 = R cos 2 pi u2, z1 = R sin 2 pi u2, R = sqrt(-2 ln u1).  ln, cos
+// and sin are float64 functions of this library: a fixed sequence of IEEE
+// operations, each rounded once (Horner steps are fused multiply-adds), so the
+// result does not depend on the math library.
+//   ln u1, u1 = K 2^-53: K = m 2^e, m in [sqrt(1/2), sqrt(2)) (exact split);
+//     ln m = 2 atanh(s), s = (m-1)/(m+1), series through s^21;
+//     ln u1 = (e-53) ln2_hi + ((e-53) ln2_lo + ln m), ln2_hi = ln 2 cut to 40
+//     bits, so its product is exact.
+//   cos, sin of 2 pi k 2^-53: the nearest quarter turn j comes off k in
+//     integers, leaving r = k - j 2^51 (|r| <= 2^50); x = r (2 pi 2^-53), one
+//     rounding, |x| <= pi/4; Taylor series of sin through x^19 and of cos
+//     through x^18; rotate by j quarter turns (swaps and sign flips, exact).
+// ---------------------------------------------------------------------------
+constexpr double F64_LN2_HI = 0x1.62e42fefa2p-1;
+constexpr double F64_LN2_LO = 0x1.9ef35793c7673p-41;
+constexpr double F64_SQRT2 = 0x1.6a09e667f3bcdp+0;
+constexpr double F64_TWO_PI_2M53 = 0x1.921fb54442d18p-51;  // float64(2 pi) * 2^-53
+
+__device__ __forceinline__ double ln_u1_f64(uint64_t K) {
+    // K <= 2^53, so its float64 value is exact; frexp splits it exactly
+    const double Kd = fma((double)(uint32_t)(K >> 32), 0x1p32, (double)(uint32_t)K);
+    int e = __builtin_amdgcn_frexp_exp(Kd) - 1;                // 2^e <= K < 2^(e+1)
+    double m = 2.0 * __builtin_amdgcn_frexp_mant(Kd);          // [1, 2)
+    if (m >= F64_SQRT2) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double P = 1.0 / 21.0;
+    P = fma(P, z, 1.0 / 19.0);
+    P = fma(P, z, 1.0 / 17.0);
+    P = fma(P, z, 1.0 / 15.0);
+    P = fma(P, z, 1.0 / 13.0);
+    P = fma(P, z, 1.0 / 11.0);
+    P = fma(P, z, 1.0 / 9.0);
+    P = fma(P, z, 1.0 / 7.0);
+    P = fma(P, z, 1.0 / 5.0);
+    P = fma(P, z, 1.0 / 3.0);
+    const double t = 2.0 * s;
+    const double ln_m = fma(t, z * P, t);
+    const double E = (double)(e - 53);
+    return fma(E, F64_LN2_HI, fma(E, F64_LN2_LO, ln_m));
+}
+
+__device__ __forceinline__ void sincos_turn_f64(uint64_t k, double &c, double &s) {
+    const uint64_t j = (k + (1ull << 50)) >> 51;                // 0..4
+    const int64_t r = (int64_t)k - (int64_t)(j << 51);           // [-2^50, 2^50]
+    const double x = (double)r * F64_TWO_PI_2M53;
+    const double z = x * x;
+    double S = -1.0 / 121645100408832000.0;
+    S = fma(S, z, 1.0 / 355687428096000.0);
+    S = fma(S, z, -1.0 / 1307674368000.0);
+    S = fma(S, z, 1.0 / 6227020800.0);
+    S = fma(S, z, -1.0 / 39916800.0);
+    S = fma(S, z, 1.0 / 362880.0);
+    S = fma(S, z, -1.0 / 5040.0);
+    S = fma(S, z, 1.0 / 120.0);
+    S = fma(S, z, -1.0 / 6.0);
+    const double sn = fma(x * z, S, x);
+    double C = 1.0 / 6402373705728000.0;
+    C = fma(C, z, -1.0 / 20922789888000.0);
+    C = fma(C, z, 1.0 / 87178291200.0);
+    C = fma(C, z, -1.0 / 479001600.0);
+    C = fma(C, z, 1.0 / 3628800.0);
+    C = fma(C, z, -1.0 / 40320.0);
+    C = fma(C, z, 1.0 / 720.0);
+    C = fma(C, z, -1.0 / 24.0);
+    C = fma(C, z, 1.0 / 2.0);
+    const double cs = fma(-z, C, 1.0);
+    const uint32_t q = (uint32_t)j & 3u;
+    const double cr = (q & 1u) ? sn : cs;
+    const double sr = (q & 1u) ? cs : sn;
+    c = (q == 1u || q == 2u) ? -cr : cr;
+    s = (q >= 2u) ? -sr : sr;
+}
+
+__device__ __forceinline__ void normal_pair_f64(uint32_t w0, uint32_t w1, uint32_t w2,
+                                                uint32_t w3, double &z0, double &z1) {
+    const uint64_t x = ((uint64_t)w1 << 32) | w0;
+    const uint64_t y = ((uint64_t)w3 << 32) | w2;
+    const double l = ln_u1_f64((x >> 11) + 1);
+    const double R = sqrt(fma(-2.0, l, 0.0));  // -2 ln u1 exactly; u1 = 1 gives +0
+    double c, s;
+    sincos_turn_f64(y >> 11, c, s);
+    z0 = R * c;
+    z1 = R * s;
+}
+
 // Convert a block of four words to the output words of its samples (bit
 // patterns): four float32/u32 samples, or two float64 samples (little-endian
-// word order) for D_F64U.
+// word order) for D_F64U and D_F64N.
 template <int D>
 __device__ __forceinline__ void convert4(uint32_t w[4]) {
     if constexpr (D == D_UNIFORM) {
@@ -430,6 +522,11 @@ __device__ __forceinline__ void convert4(uint32_t w[4]) {
         // halves taken as 32-bit values (no 64-bit view of w, which kept the
         // array out of registers)
         const double a = u01_f64(w[0], w[1]), b = u01_f64(w[2], w[3]);
+        w[0] = (uint32_t)__double2loint(a); w[1] = (uint32_t)__double2hiint(a);
+        w[2] = (uint32_t)__double2loint(b); w[3] = (uint32_t)__double2hiint(b);
+    } else if constexpr (D == D_F64N) {
+        double a, b;
+        normal_pair_f64(w[0], w[1], w[2], w[3], a, b);
         w[0] = (uint32_t)__double2loint(a); w[1] = (uint32_t)__double2hiint(a);
         w[2] = (uint32_t)__double2loint(b); w[3] = (uint32_t)__double2hiint(b);
     }

@@ -110,7 +110,8 @@ static void *pick_d(int dist, bool units, bool nt) {
     case D_U32: return pick<G, D_U32>(units, nt);
     case D_UNIFORM: return pick<G, D_UNIFORM>(units, nt);
     case D_NORMAL: return pick<G, D_NORMAL>(units, nt);
-    default: return pick<G, D_F64U>(units, nt);
+    case D_F64U: return pick<G, D_F64U>(units, nt);
+    default: return pick<G, D_F64N>(units, nt);
     }
 }
 

@@ -12,11 +12,12 @@ namespace orng {
 
 constexpr uint64_t PERIOD = 1ull << 32;
 
-// Stream words per sample: a float64 uniform sample is made from the word
-// pair (2p, 2p+1), every other distribution from one word.  The public calls
+// Stream words per sample: a float64 sample is made from the word pair
+// (2p, 2p+1) (a float64 normal pair from the block 4m..4m+3), every other
+// distribution from one word.  The public calls
 // take offsets and counts in samples and convert them to words (positions)
 // once; below that, every launcher and kernel works in words.
-inline uint64_t words_per_sample(int dist) { return dist == D_F64U ? 2 : 1; }
+inline uint64_t words_per_sample(int dist) { return dist == D_F64U || dist == D_F64N ? 2 : 1; }
 inline uint64_t sample_limit(int dist) { return PERIOD / words_per_sample(dist); }
 
 // Launch knobs.  0 means "choose automatically".

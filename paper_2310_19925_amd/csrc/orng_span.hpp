@@ -193,7 +193,11 @@ __device__ __forceinline__ uint64_t xcd_tile(uint64_t b, uint64_t grid) {
 }
 
 // Runtime (gen, dist) dispatch for kernels whose requests mix generators.
-template <bool NT>
+// F64N selects whether the float64 normal cases are compiled in: their code
+// needs more than twice the vector registers of every other case, and a
+// kernel's register count (so its occupancy) is that of its largest case, so
+// the launchers use the variant without them unless a request needs them.
+template <bool NT, bool F64N>
 __device__ __forceinline__ void process_span_any(int gen, int dist, const KeySched &ks,
                                                  uint32_t ctr, char *base, uint64_t p0,
                                                  uint64_t pend, uint64_t span, uint32_t unroll,
@@ -210,7 +214,15 @@ __device__ __forceinline__ void process_span_any(int gen, int dist, const KeySch
         ORNG_CASE(4, 0) ORNG_CASE(4, 1) ORNG_CASE(4, 2) ORNG_CASE(4, 3)
         ORNG_CASE(5, 0) ORNG_CASE(5, 1) ORNG_CASE(5, 2) ORNG_CASE(5, 3)
         ORNG_CASE(6, 0) ORNG_CASE(6, 1) ORNG_CASE(6, 2) ORNG_CASE(6, 3)
-        default: break;
+        default:
+            if constexpr (F64N) {
+                switch (gen * NDIST + dist) {
+                    ORNG_CASE(0, 4) ORNG_CASE(1, 4) ORNG_CASE(2, 4) ORNG_CASE(3, 4)
+                    ORNG_CASE(4, 4) ORNG_CASE(5, 4) ORNG_CASE(6, 4)
+                    default: break;
+                }
+            }
+            break;
     }
 #undef ORNG_CASE
 }

@@ -30,38 +30,45 @@ static Tuned g_tuned[NGEN][NDIST];
 static bool g_tuned_init = false;
 
 // Measured on MI355X by orng_autotune (one entry per gen x dist, in
-// enum order: u32, f32 uniform, f32 normal, f64 uniform): wg unroll max_wgs nontemporal | batched wg unroll chunk wgs/CU
+// enum order: u32, f32 uniform, f32 normal, f64 uniform, f64 normal): wg unroll max_wgs nontemporal | batched wg unroll chunk wgs/CU
 // (wgs/CU 0 = static one-workgroup-per-tile schedule).
 static const uint32_t kDefaultTable[NGEN * NDIST][8] = {
         {64, 4, 0, 2, 512, 8, 1, 0},
         {64, 4, 0, 1, 512, 8, 1, 0},
         {512, 2, 8192, 1, 128, 16, 1, 0},
         {64, 4, 0, 2, 512, 8, 1, 0},
+        {512, 2, 8192, 1, 128, 16, 1, 0},
         {256, 8, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 2, 128, 16, 1, 0},
         {512, 8, 8192, 1, 256, 16, 1, 0},
+        {512, 8, 8192, 2, 128, 16, 1, 0},
         {512, 4, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 1, 128, 16, 1, 0},
         {512, 4, 8192, 2, 128, 16, 1, 0},
         {512, 4, 8192, 1, 256, 16, 1, 0},
+        {512, 4, 8192, 2, 128, 16, 1, 0},
         {64, 4, 0, 1, 256, 8, 1, 0},
         {64, 8, 0, 1, 256, 8, 1, 0},
         {256, 2, 8192, 1, 128, 16, 1, 0},
         {256, 8, 0, 1, 256, 16, 1, 0},
+        {256, 2, 8192, 1, 128, 16, 1, 0},
         {64, 64, 0, 2, 512, 1, 1, 0},
         {64, 64, 0, 2, 512, 1, 1, 0},
         {256, 64, 0, 1, 128, 1, 1, 0},
         {512, 64, 0, 2, 128, 1, 1, 8},
+        {256, 64, 0, 1, 128, 1, 1, 0},
         // 13-round Threefry
         {64, 8, 0, 1, 256, 8, 1, 0},
         {512, 4, 8192, 1, 128, 16, 1, 0},
         {512, 2, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 1, 256, 16, 1, 0},
+        {512, 2, 8192, 1, 128, 16, 1, 0},
         {256, 8, 0, 2, 256, 8, 1, 0},
         {512, 8, 8192, 1, 128, 16, 1, 0},
         {256, 8, 0, 1, 256, 16, 1, 0},
         {256, 8, 8192, 1, 256, 16, 1, 0},
+        {256, 8, 0, 1, 256, 16, 1, 0},
 };
 
 static Tuned default_tuned(int gen, int dist) {

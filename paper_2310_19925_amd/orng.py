@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "liborng.so")
 
 PHILOX4X32_10, THREEFRY4X32_20, THREEFRY2X64_20, SQUARES32, TYCHE = range(5)
 THREEFRY4X32_13, THREEFRY2X64_13 = 5, 6
-U32, F32_UNIFORM, F32_NORMAL, F64_UNIFORM = range(4)
+U32, F32_UNIFORM, F32_NORMAL, F64_UNIFORM, F64_NORMAL = range(5)
 OK, EINVAL, ERANGE, ENOMEM, EAGAIN, EBUSY, EHIP, ENOENT = 0, -1, -2, -3, -4, -5, -6, -7
 
 
@@ -307,12 +307,13 @@ def orng_serve_destroy(srv):
 # -------- convenience wrappers that allocate the output tensor ---------------
 def _torch_dtype(dist):
     import torch
-    return {U32: torch.int32, F64_UNIFORM: torch.float64}.get(dist, torch.float32)
+    return {U32: torch.int32, F64_UNIFORM: torch.float64, F64_NORMAL: torch.float64}.get(
+        dist, torch.float32)
 
 
 def fill(gen, dist, seed, ctr, offset, n, device="cuda", stream=None):
     """Returns a new device tensor (uint32 viewed as int32 for U32, float64 for
-    F64_UNIFORM, float32 otherwise)."""
+    F64_UNIFORM and F64_NORMAL, float32 otherwise)."""
     import torch
     dt = _torch_dtype(dist)
     out = torch.empty(n, dtype=dt, device=device)

@@ -83,7 +83,7 @@ def test_fill_errors(R):
         R.orng_fill(7, 0, 1, 1, 0, 4, out)
     assert e.value.status == R.EINVAL
     with pytest.raises(R.OrngError) as e:
-        R.orng_fill(0, 4, 1, 1, 0, 4, out)
+        R.orng_fill(0, 5, 1, 1, 0, 4, out)
     assert e.value.status == R.EINVAL
     with pytest.raises(R.OrngError) as e:
         R.orng_fill(0, 0, 1, 1, 2**32 - 3, 4, out)

@@ -38,7 +38,7 @@ FAKE = 0x10000  # a non-null, 16-byte aligned address that is never dereferenced
 
 def test_fill_validation(L):
     assert L.orng_fill(-1, 0, 1, 1, 0, 4, FAKE, None) == EINVAL
-    assert L.orng_fill(0, 4, 1, 1, 0, 4, FAKE, None) == EINVAL
+    assert L.orng_fill(0, 5, 1, 1, 0, 4, FAKE, None) == EINVAL
     # float64 uniform: samples end at 2^31, 8-byte alignment
     assert L.orng_fill(0, 3, 1, 1, 2**31 - 3, 4, FAKE, None) == ERANGE
     assert L.orng_fill(0, 3, 1, 1, 2**31 + 1, 0, FAKE, None) == ERANGE
@@ -119,7 +119,7 @@ def test_batched_validation_rejects_whole_batch(L, fn):
     f = getattr(L, fn)
     cases = [
         ([(0, 0, 0, 16, FAKE, 0), (7, 0, 0, 16, FAKE, 0)], EINVAL),     # bad generator
-        ([(0, 4, 0, 16, FAKE, 0)], EINVAL),                              # bad distribution
+        ([(0, 5, 0, 16, FAKE, 0)], EINVAL),                              # bad distribution
         ([(0, 0, 0, 16, FAKE, 1)], EINVAL),                              # reserved flags
         ([(0, 0, 2**32 - 8, 16, FAKE, 0)], ERANGE),                      # past the period
         ([(0, 0, 0, 16, 0, 0)], EINVAL),                                 # NULL output
@@ -181,7 +181,7 @@ def test_tune_table_loader(L, tmp_path):
     good.write_text("# header\n0 0 256 2 0 2 256 4 1 0\n4 1 256 64 0 2 256 1 1 0\n")
     assert L.orng_tune_load(str(good).encode()) == 0
     assert L.orng_autotune(7, 0, None) == EINVAL
-    assert L.orng_autotune(0, 4, None) == EINVAL
+    assert L.orng_autotune(0, 5, None) == EINVAL
 
 
 def test_serve_create_validation(L):
