@@ -97,16 +97,18 @@ def roofs(gen, dist, n, ms):
 # calibration factors a 1 GiB device copy gives for each counter.  Valid only
 # for the kernel sources and launch table they were measured on: bench.py
 # reports null traffic when the hash of those sources differs.
-TRAFFIC_SRC_SHA = "b169ccc5402596e0"
-TRAFFIC_FACTORS = (1.9999241857658536, 1.0)  # FETCH, WRITE
+TRAFFIC_SRC_SHA = "0b67a570d0fd0a85"
+TRAFFIC_FACTORS = (1.9999218017636564, 1.0)  # FETCH, WRITE
 TRAFFIC_KIB = {
-    (0, 0): (77.125, 4194304.0), (0, 1): (51.75, 4194586.875), (0, 2): (79.9375, 4194327.875), (0, 3): (44.0, 4194304.0),
-    (1, 0): (56.5, 4194325.5), (1, 1): (56.5, 4194304.125), (1, 2): (72.1875, 4194304.0), (1, 3): (49.5, 4194330.875),
-    (2, 0): (49.0, 4194326.5), (2, 1): (55.5, 4194312.875), (2, 2): (67.5, 4194304.0), (2, 3): (48.0, 4194306.375),
-    (3, 0): (52.0, 4194333.25), (3, 1): (52.5, 4194304.0), (3, 2): (101.8125, 4194325.25), (3, 3): (51.5, 4195830.25),
-    (4, 0): (37.125, 4194304.0), (4, 1): (33.6875, 4194304.0), (4, 2): (41.75, 4194353.125), (4, 3): (68.5625, 4194304.0),
-    (5, 0): (49.5, 4194849.75), (5, 1): (52.0, 4194355.25), (5, 2): (63.5, 4194304.0), (5, 3): (54.0, 4194867.25),
-    (6, 0): (53.0, 4194304.0), (6, 1): (55.0, 4197380.25), (6, 2): (59.5, 4194304.0), (6, 3): (50.0, 4195657.0),
+    (0, 0): (87.75, 4194304.0), (0, 1): (52.25, 4194575.625), (0, 2): (86.6875, 4194321.5), (0, 3): (49.5, 4194304.0),
+    (0, 4): (64.5, 4194305.5), (1, 0): (53.6875, 4194307.5), (1, 1): (65.4375, 4194316.625), (1, 2): (63.4375, 4194304.0),
+    (1, 3): (57.0, 4194318.5), (1, 4): (69.5, 4194304.0), (2, 0): (55.5, 4194323.625), (2, 1): (53.0, 4194322.125),
+    (2, 2): (62.5, 4194304.0), (2, 3): (57.5, 4194322.5), (2, 4): (71.0, 4194304.0), (3, 0): (52.0, 4194304.125),
+    (3, 1): (38.0, 4194338.0), (3, 2): (105.75, 4194319.25), (3, 3): (53.0, 4195531.875), (3, 4): (66.5, 4194321.125),
+    (4, 0): (40.1875, 4194304.0), (4, 1): (32.1875, 4194304.0), (4, 2): (41.4375, 4194324.5), (4, 3): (67.0625, 4194304.0),
+    (4, 4): (40.125, 4194320.75), (5, 0): (47.0, 4194332.875), (5, 1): (54.0, 4194389.0), (5, 2): (62.5, 4194359.25),
+    (5, 3): (53.0, 4196751.5), (5, 4): (64.5, 4194308.625), (6, 0): (51.0, 4194304.0), (6, 1): (46.0, 4194840.625),
+    (6, 2): (53.5, 4194342.875), (6, 3): (48.5, 4195149.75), (6, 4): (69.0, 4194306.75),
 }
 
 
