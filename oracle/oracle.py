@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "orng_oracle.cc")
 LIB = os.path.join(HERE, "liborng_oracle.so")
 
-PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE, THREEFRY4X32_13, THREEFRY2X64_13 = range(7)
+(PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE, THREEFRY4X32_13, THREEFRY2X64_13, TYCHE_I,
+ SQUARES64) = range(9)
 U32, F32_UNIFORM, F32_NORMAL, F64_UNIFORM, F64_NORMAL = range(5)
 GENS = (PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE)
 DISTS = (U32, F32_UNIFORM, F32_NORMAL)  # the float32/u32 set; F64_UNIFORM is separate
@@ -60,6 +61,10 @@ def lib():
             "oracle_tyche_mix": (None, [P32]),
             "oracle_tyche_init": (None, [u64, u32, u32, P32]),
             "oracle_tyche_next": (u32, [P32]),
+            "oracle_tyche_mix_i": (None, [P32]),
+            "oracle_tyche_i_init": (None, [u64, u32, u32, P32]),
+            "oracle_tyche_i_next": (u32, [P32]),
+            "oracle_squares64": (u64, [u64, u64]),
             "oracle_word": (u32, [i32, u64, u32, u64]),
             "oracle_sample": (None, [i32, i32, u64, u32, u64, vp]),
             "oracle_u01": (f32, [u32]),
@@ -360,3 +365,25 @@ def sincos_turn_f64_n(k):
     s = np.empty(k.shape, np.float64)
     lib().oracle_sincos_turn_f64_n(k.ctypes.data, k.size, c.ctypes.data, s.ctypes.data)
     return c, s
+
+
+def tyche_mix_i(state):
+    st = _arr32(state)
+    lib().oracle_tyche_mix_i(st)
+    return list(st)
+
+
+def tyche_i_init(seed, c_xor, d_xor):
+    st = (C.c_uint32 * 4)()
+    lib().oracle_tyche_i_init(seed, c_xor & 0xFFFFFFFF, d_xor & 0xFFFFFFFF, st)
+    return list(st)
+
+
+def tyche_i_stream(seed, c_xor, d_xor, count):
+    st = (C.c_uint32 * 4)()
+    lib().oracle_tyche_i_init(seed, c_xor & 0xFFFFFFFF, d_xor & 0xFFFFFFFF, st)
+    return [lib().oracle_tyche_i_next(st) for _ in range(count)]
+
+
+def squares64(ctr, key):
+    return lib().oracle_squares64(ctr, key)

@@ -152,15 +152,24 @@ void words_range(int gen, uint64_t seed, uint32_t ctr, uint64_t p0, uint64_t cou
         const uint64_t key = oracle_squares_key(seed);
         for (uint64_t p = p0; p < p1; ++p)
             dst[p - p0] = oracle_squares32(((uint64_t)ctr << 32) | p, key);
-    } else if (gen == OR_TYCHE) {
+    } else if (gen == OR_SQUARES64) {
+        /* word p is the low (p even) or high half of call p/2 */
+        const uint64_t key = oracle_squares_key(seed);
+        for (uint64_t p = p0; p < p1; ++p) {
+            const uint64_t v = oracle_squares64(((uint64_t)ctr << 32) | (p / 2), key);
+            dst[p - p0] = (uint32_t)(p & 1 ? v >> 32 : v);
+        }
+    } else if (gen == OR_TYCHE || gen == OR_TYCHE_I) {
+        const bool inv = gen == OR_TYCHE_I;
         /* walk every substream (tile, lane) that owns a position in range */
         for (uint64_t t = p0 / TYCHE_TILE; t * TYCHE_TILE < p1; ++t) {
             for (uint64_t l = 0; l < TYCHE_LANES; ++l) {
                 uint32_t st[4];
-                oracle_tyche_init(seed, (uint32_t)(t * TYCHE_LANES + l), ctr, st);
+                if (inv) oracle_tyche_i_init(seed, (uint32_t)(t * TYCHE_LANES + l), ctr, st);
+                else oracle_tyche_init(seed, (uint32_t)(t * TYCHE_LANES + l), ctr, st);
                 for (uint64_t k = 0; k < TYCHE_BLOCKS; ++k) {
                     for (uint64_t w = 0; w < 4; ++w) {
-                        uint32_t v = oracle_tyche_next(st);
+                        uint32_t v = inv ? oracle_tyche_i_next(st) : oracle_tyche_next(st);
                         uint64_t p = t * TYCHE_TILE + (k * TYCHE_LANES + l) * 4 + w;
                         if (p >= p0 && p < p1) dst[p - p0] = v;
                     }
@@ -232,7 +241,7 @@ void samples_range(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t p0, 
     }
 }
 
-bool valid_gen(int g) { return g >= OR_PHILOX && g <= OR_THREEFRY2X64_13; }
+bool valid_gen(int g) { return g >= OR_PHILOX && g <= OR_SQUARES64; }
 bool valid_dist(int d) { return d >= OR_U32 && d <= OR_F64_NORMAL; }
 /* bytes per sample, and stream positions (words) per sample */
 bool is_f64(int dist) { return dist == OR_F64_UNIFORM || dist == OR_F64_NORMAL; }
@@ -375,15 +384,74 @@ uint32_t oracle_tyche_next(uint32_t st[4]) {
     return st[1];
 }
 
+/* ---------------------------------------------------------------------------
+ * Tyche-i (Neves, Araujo, PPAM 2011: the variant of Tyche built on the
+ * inverse of MIX).  Reading: MIX-i undoes MIX's four steps in reverse order
+ * (so b = rotr(b, 7) ^ c; c -= d; d = rotr(d, 8) ^ a; a -= b; then the same
+ * with 12 and 16); seeding and output are Tyche's with MIX-i in place of MIX
+ * (twenty rounds, then one round per output word, returning b), and the
+ * stream layout is Tyche's.  A Tyche-i stream is therefore a Tyche state
+ * orbit walked backwards.  Pinned in the test-suite: MIX-i inverts the pinned
+ * MIX on random states, and twenty pinned MIX rounds take a Tyche-i seeded
+ * state back to the raw seeding words.  Which word is output is parity
+ * unpinned (no implementation in the container).
+ * ------------------------------------------------------------------------- */
+void oracle_tyche_mix_i(uint32_t st[4]) {
+    uint32_t a = st[0], b = st[1], c = st[2], d = st[3];
+    b = rotl32(b, 25) ^ c; c -= d;
+    d = rotl32(d, 24) ^ a; a -= b;
+    b = rotl32(b, 20) ^ c; c -= d;
+    d = rotl32(d, 16) ^ a; a -= b;
+    st[0] = a; st[1] = b; st[2] = c; st[3] = d;
+}
+
+void oracle_tyche_i_init(uint64_t seed, uint32_t c_xor, uint32_t d_xor, uint32_t st[4]) {
+    st[0] = (uint32_t)(seed >> 32);
+    st[1] = (uint32_t)seed;
+    st[2] = TYCHE_C0 ^ c_xor;
+    st[3] = TYCHE_D0 ^ d_xor;
+    for (int i = 0; i < 20; ++i) oracle_tyche_mix_i(st);
+}
+
+uint32_t oracle_tyche_i_next(uint32_t st[4]) {
+    oracle_tyche_mix_i(st);
+    return st[1];
+}
+
+/* ---------------------------------------------------------------------------
+ * Squares64 (Widynski, arXiv:2004.06278, the five-round 64-bit output form):
+ * rounds 1-4 as Squares32, keeping the full 64-bit value t of round 4; round
+ * 5 squares the swapped t, adds y, and XORs its high half into t's low half.
+ * Stream layout (reading, as for Squares32 with two words per call): word p is
+ * the low (p even) or high (p odd) half of squares64((ctr << 32) | p/2, K),
+ * K the Squares key of the seed.  Pinned in the test-suite: the high half of
+ * every output is the (separately transcribed) Squares32 output of the same
+ * counter and key.  Otherwise parity unpinned.
+ * ------------------------------------------------------------------------- */
+uint64_t oracle_squares64(uint64_t ctr, uint64_t key) {
+    uint64_t y = ctr * key;
+    uint64_t z = y + key;
+    uint64_t x = y;
+    x = x * x + y; x = (x >> 32) | (x << 32); /* round 1 */
+    x = x * x + z; x = (x >> 32) | (x << 32); /* round 2 */
+    x = x * x + y; x = (x >> 32) | (x << 32); /* round 3 */
+    const uint64_t t = x * x + z;             /* round 4 */
+    x = (t >> 32) | (t << 32);
+    return t ^ ((x * x + y) >> 32);           /* round 5 */
+}
+
 uint32_t oracle_word(int gen, uint64_t seed, uint32_t ctr, uint64_t p) {
     uint32_t w = 0;
-    if (gen == OR_TYCHE) {
+    if (gen == OR_TYCHE || gen == OR_TYCHE_I) {
         /* direct evaluation of the layout: fresh instance, step to the word */
+        const bool inv = gen == OR_TYCHE_I;
         const uint64_t t = p / TYCHE_TILE, r = p % TYCHE_TILE;
         const uint64_t l = (r / 4) % TYCHE_LANES, k = r / 256, wi = r % 4;
         uint32_t st[4];
-        oracle_tyche_init(seed, (uint32_t)(t * TYCHE_LANES + l), ctr, st);
-        for (uint64_t i = 0; i <= 4 * k + wi; ++i) w = oracle_tyche_next(st);
+        if (inv) oracle_tyche_i_init(seed, (uint32_t)(t * TYCHE_LANES + l), ctr, st);
+        else oracle_tyche_init(seed, (uint32_t)(t * TYCHE_LANES + l), ctr, st);
+        for (uint64_t i = 0; i <= 4 * k + wi; ++i)
+            w = inv ? oracle_tyche_i_next(st) : oracle_tyche_next(st);
         return w;
     }
     words_range(gen, seed, ctr, p, 1, &w);

@@ -41,7 +41,7 @@ extern "C" {
 /* generator and distribution codes (same numbering as the public API; the
    numbers are part of the interface, not shared code) */
 enum { OR_PHILOX = 0, OR_THREEFRY4X32 = 1, OR_THREEFRY2X64 = 2, OR_SQUARES = 3, OR_TYCHE = 4,
-       OR_THREEFRY4X32_13 = 5, OR_THREEFRY2X64_13 = 6 };
+       OR_THREEFRY4X32_13 = 5, OR_THREEFRY2X64_13 = 6, OR_TYCHE_I = 7, OR_SQUARES64 = 8 };
 enum { OR_U32 = 0, OR_F32_UNIFORM = 1, OR_F32_NORMAL = 2, OR_F64_UNIFORM = 3, OR_F64_NORMAL = 4 };
 
 /* --- raw generator cores ------------------------------------------------ */
@@ -55,6 +55,10 @@ uint64_t oracle_squares_key(uint64_t seed);
 void oracle_tyche_mix(uint32_t st[4]);             /* st = {a, b, c, d}, in place */
 void oracle_tyche_init(uint64_t seed, uint32_t c_xor, uint32_t d_xor, uint32_t st[4]);
 uint32_t oracle_tyche_next(uint32_t st[4]);        /* one MIX, returns b */
+void oracle_tyche_mix_i(uint32_t st[4]);           /* the inverse of MIX, in place */
+void oracle_tyche_i_init(uint64_t seed, uint32_t c_xor, uint32_t d_xor, uint32_t st[4]);
+uint32_t oracle_tyche_i_next(uint32_t st[4]);      /* one inverse MIX, returns b */
+uint64_t oracle_squares64(uint64_t ctr, uint64_t key);  /* five rounds, 64-bit output */
 
 /* --- stream model -------------------------------------------------------- */
 /* word at position p of stream (seed, ctr) of generator gen */

@@ -55,7 +55,7 @@ def test_full_int32_span(O):
     assert got.min() < -2**31 + 2**20 and got.max() > 2**31 - 2**20
 
 
-@pytest.mark.parametrize("gen", range(7))
+@pytest.mark.parametrize("gen", range(9))
 def test_no_remainder_bias(O, gen):
     """r = 3 * 2^30: the remainder of one 32-bit word would put half of all
     samples in the lowest third; here each third holds a third."""
@@ -67,7 +67,7 @@ def test_no_remainder_bias(O, gen):
     assert np.all(np.abs(frac - 1 / 3) < 5 * sd), frac
 
 
-@pytest.mark.parametrize("gen", range(7))
+@pytest.mark.parametrize("gen", range(9))
 def test_die_frequencies(O, gen):
     from scipy import stats
     got = O.fill_range(gen, 77, 0, 1, 1000, 600000, 1, 7)
@@ -75,7 +75,7 @@ def test_die_frequencies(O, gen):
     assert stats.chisquare(np.bincount(got, minlength=7)[1:])[1] > 1e-4
 
 
-@pytest.mark.parametrize("gen", range(7))
+@pytest.mark.parametrize("gen", range(9))
 def test_layout_follows_the_word_stream(O, gen):
     """Sample p of a stream is built from words 2p and 2p+1 of the same
     stream; many streams are counters ctr0 + i."""
@@ -96,7 +96,7 @@ def test_layout_follows_the_word_stream(O, gen):
 def test_range_errors(O):
     O.fill_range(0, 0, 0, 1, 2**31, 0, 0, 1)
     O.fill_range(0, 0, 2**32 - 2, 2, 0, 4, 0, 1)
-    for args in [(0, 0, 0, 1, 0, 4, 5, 5), (0, 0, 0, 1, 0, 4, 6, 5), (7, 0, 0, 1, 0, 4, 0, 1),
+    for args in [(0, 0, 0, 1, 0, 4, 5, 5), (0, 0, 0, 1, 0, 4, 6, 5), (9, 0, 0, 1, 0, 4, 0, 1),
                  (0, 0, 0, 1, 2**31 - 3, 4, 0, 1), (0, 0, 2**32 - 2, 3, 0, 4, 0, 1)]:
         with pytest.raises(ValueError):
             O.fill_range(*args)
