@@ -55,7 +55,7 @@ VALU_PEAK_TSLOTS = 256 * 64 * 2.4e9 / 1e12
 #     injections x 2 (no injection after round 13): 80 / 4 words
 #   Threefry2x64-13: 12 rounds x 5 + round 1 (3) + counter add 1 + 3 x 2: 70 / 4 words
 SLOTS_GEN = {0: 38 / 4, 1: 128 / 4, 2: 109 / 4, 3: 13 + 3 / 4, 4: 12 + 20 * 12 / 256,
-             5: 80 / 4, 6: 70 / 4}
+             5: 80 / 4, 6: 70 / 4, 7: 12 + 20 * 12 / 256, 8: (5 * 3 + 2 + 1) / 2 + 3 / 4}
 SLOTS_DIST = {0: 0.0, 1: 2.0, 2: 36.5 / 2}
 # float64 uniform: two words per sample, then shift, two conversions, one
 # exact fma and one scaling (float64 operations: one slot each at the
@@ -341,8 +341,10 @@ def bench_bd2(orng, inputs, stream, dev, per_step_too=True):
 # VALU slots per 3-word micro-stream (one stream per particle and iteration):
 # one counter block for Philox/Threefry (3 of its 4 words used); three
 # Squares words plus the y product; Tyche seeds an instance (20 MIX) and runs
-# 4 more (12 slots per MIX).
-PART_SLOTS_3 = {0: 38, 1: 128, 2: 109, 3: 3 + 3 * 13, 4: 24 * 12}
+# 4 more (12 slots per MIX); the 13-round Threefry blocks; Tyche-i as Tyche;
+# Squares64 two calls (5 rounds of 3 slots, the 64-bit adds and the XOR).
+PART_SLOTS_3 = {0: 38, 1: 128, 2: 109, 3: 3 + 3 * 13, 4: 24 * 12, 5: 80, 6: 70, 7: 24 * 12,
+                8: 3 + 2 * 18}
 
 
 def bench_particles(orng, inputs, stream, dev):
@@ -353,7 +355,7 @@ def bench_particles(orng, inputs, stream, dev):
     T = (1 << 30) // (P * D)
     out = torch.empty(T * P * D, dtype=torch.int32, device=dev)
     res = []
-    for g in range(5):
+    for g in range(9):
         ms = _time_events(stream, lambda: orng.orng_particle_streams(g, 1, P, D, 1, T, out,
                                                                      stream), 3)
         words = T * P * D
@@ -510,8 +512,8 @@ def main():
     # and the 13-round Threefry variants (4 GiB each)
     extra = []
     if not args.only:
-        cases = [(g, 3) for g in range(7)] + [(g, 4) for g in range(7)] + \
-            [(g, d) for g in (5, 6) for d in range(3)]
+        cases = [(g, 3) for g in range(9)] + [(g, 4) for g in range(9)] + \
+            [(g, d) for g in (5, 6, 7, 8) for d in range(3)]
         for g, d in cases:
             ns = n // 2 if d in (3, 4) else n
             ms = _time_events(stream, lambda: orng.orng_fill(g, d, seed, 0, 0, ns, out, stream), 3)
@@ -523,7 +525,7 @@ def main():
                           "valu_frac": rf["valu_frac"], "binding": rf["binding"],
                           "binding_frac": rf["binding_frac"]})
         # integers in [lo, hi), 2^30 int32 samples each
-        for g in range(7):
+        for g in range(9):
             ms = _time_events(stream, lambda: orng.orng_fill_range(
                 g, seed, 0, 1, 0, n, RANGE_LO, RANGE_HI, out, stream), 3)
             rf = roofs(g, "range", n, ms)

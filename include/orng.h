@@ -44,7 +44,9 @@ enum {
     ORNG_SQUARES32 = 3,
     ORNG_TYCHE = 4,
     ORNG_THREEFRY4X32_13 = 5, /* the Threefry rounds stopped after round 13 */
-    ORNG_THREEFRY2X64_13 = 6
+    ORNG_THREEFRY2X64_13 = 6,
+    ORNG_TYCHE_I = 7,         /* Tyche on the inverse of its mixing round */
+    ORNG_SQUARES64 = 8        /* five-round Squares, 64 bits (two words) per call */
 };
 
 /* distributions; samples are 4 bytes, 8 for the two float64 ones */
@@ -96,6 +98,10 @@ enum {
  *                    r = p % 16384 is output 4*(r/256) + r%4 of the Tyche
  *                    instance seeded with (seed, ctr) whose c word is XORed
  *                    with t*64 + (r/4)%64.
+ *   Tyche-i        : the Tyche layout and seeding with MIX-i, the inverse of
+ *                    Tyche's MIX (its four steps undone in reverse order)
+ *   Squares64      : word p = low (p even) or high half of
+ *                    squares64(counter (ctr << 32) | p/2, key K(seed))
  * Arguments: gen, dist (enums above); d_out: device buffer of n samples
  * (n * 4 bytes, 4-byte aligned; n * 8 bytes, 8-byte aligned for the float64
  * distributions).

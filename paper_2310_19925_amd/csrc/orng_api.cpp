@@ -38,7 +38,7 @@ static int hip_status(hipError_t e) {
     return ORNG_EHIP;
 }
 
-static bool valid_gen(int g) { return g >= ORNG_PHILOX4X32_10 && g <= ORNG_THREEFRY2X64_13; }
+static bool valid_gen(int g) { return g >= ORNG_PHILOX4X32_10 && g <= ORNG_SQUARES64; }
 static bool valid_dist(int d) { return d >= ORNG_U32 && d <= ORNG_F64_NORMAL; }
 
 }  // namespace orng

@@ -228,7 +228,7 @@ static void *batched_kernel(const BatchShape &s, bool f64n) {
 }
 
 int validate_request(const orng_req_t &r) {
-    if (r.gen > ORNG_THREEFRY2X64_13 || r.dist > ORNG_F64_NORMAL || r.flags != 0) return ORNG_EINVAL;
+    if (r.gen > ORNG_SQUARES64 || r.dist > ORNG_F64_NORMAL || r.flags != 0) return ORNG_EINVAL;
     const uint64_t k = words_per_sample((int)r.dist), lim = sample_limit((int)r.dist);
     if (r.offset > lim || r.n > lim - r.offset) return ORNG_ERANGE;
     if (r.n == 0) return ORNG_OK;
@@ -347,7 +347,7 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     uint32_t unroll_of[NGEN][NDIST];  // one table lookup per pair, not per request
     for (int g = 0; g < NGEN; ++g)
         for (int d = 0; d < NDIST; ++d)
-            unroll_of[g][d] = g == G_TYCHE ? 64 : tuned_fill(g, d).b_unroll;
+            unroll_of[g][d] = tyche_like(g) ? 64 : tuned_fill(g, d).b_unroll;
     // The workgroup shape, and so the tile size, follows the first request
     // with work; this pass finds it before tiling.
     size_t first_live = nreq;

@@ -23,9 +23,13 @@
 namespace orng {
 
 enum GenId : int { G_PHILOX = 0, G_TF4X32 = 1, G_TF2X64 = 2, G_SQUARES = 3, G_TYCHE = 4,
-                   G_TF4X32_13 = 5, G_TF2X64_13 = 6 };
+                   G_TF4X32_13 = 5, G_TF2X64_13 = 6, G_TYCHE_I = 7, G_SQUARES64 = 8 };
 enum DistId : int { D_U32 = 0, D_UNIFORM = 1, D_NORMAL = 2, D_F64U = 3, D_F64N = 4 };
-constexpr int NGEN = 7, NDIST = 5;
+constexpr int NGEN = 9, NDIST = 5;
+
+// Tyche and Tyche-i share the tile layout (no random access within a
+// substream); every other generator is counter-based with 4-word blocks.
+__host__ __device__ constexpr bool tyche_like(int g) { return g == G_TYCHE || g == G_TYCHE_I; }
 
 // Per-launch key material, uniform across the grid.
 struct KeySched {
@@ -248,20 +252,56 @@ __device__ __forceinline__ void squares_block(uint32_t blk, uint32_t ctr, uint64
     }
 }
 
+// Squares64: rounds 1-4 as Squares32 but keeping round 4's full value t;
+// round 5 squares t with its halves swapped and adds y, and its high half is
+// XORed into t's low half.  Counter ((stream counter << 32) | call), two words
+// per call (low half first), so block blk is calls 2 blk and 2 blk + 1.
+__device__ __forceinline__ void squares64_rounds(uint64_t y, uint64_t z, uint32_t &lo,
+                                                 uint32_t &hi) {
+    uint32_t l, h, l5, h5;
+    sq_add((uint32_t)y, (uint32_t)(y >> 32), y, l, h);  // round 1: x = y
+    sq_add(h, l, z, l, h);                              // round 2
+    sq_add(h, l, y, l, h);                              // round 3
+    sq_add(h, l, z, l, h);                              // round 4: t = (h, l)
+    sq_add(h, l, y, l5, h5);                            // round 5
+    lo = l ^ h5;
+    hi = h;
+}
+
+__device__ __forceinline__ void squares64_block(uint32_t blk, uint32_t ctr, uint64_t key,
+                                                uint32_t w[4]) {
+    const uint32_t q = blk << 1;
+    const uint32_t kl = (uint32_t)key, kh = (uint32_t)(key >> 32);
+    const uint64_t y = (uint64_t)q * kl + ((uint64_t)(q * kh + ctr * kl) << 32);
+    const uint64_t z = y + key;
+    squares64_rounds(y, z, w[0], w[1]);
+    squares64_rounds(z, z + key, w[2], w[3]);
+}
+
 // ---------------------------------------------------------------------------
 // Tyche.  MIX is the ChaCha quarter round; seeding puts (hi seed, lo seed,
 // floor(2^32/phi) ^ substream, floor(2^32/pi) ^ counter) in (a, b, c, d) and
 // mixes twenty times; each output mixes once and returns b.  Stream layout:
 // tiles of 16384 words; in tile t, lane l (0..63) owns blocks k*64 + l,
 // k = 0..63, and produces them from substream t*64 + l in order.
+// Tyche-i (INV): the same with MIX-i, the inverse of MIX (its four steps
+// undone in reverse order), so its stream walks Tyche's state orbit backwards.
 // ---------------------------------------------------------------------------
-struct Tyche {
+template <bool INV>
+struct TycheT {
     uint32_t a, b, c, d;
     __device__ __forceinline__ void mix() {
-        a += b; d = rotl32(d ^ a, 16);
-        c += d; b = rotl32(b ^ c, 12);
-        a += b; d = rotl32(d ^ a, 8);
-        c += d; b = rotl32(b ^ c, 7);
+        if constexpr (!INV) {
+            a += b; d = rotl32(d ^ a, 16);
+            c += d; b = rotl32(b ^ c, 12);
+            a += b; d = rotl32(d ^ a, 8);
+            c += d; b = rotl32(b ^ c, 7);
+        } else {
+            b = rotl32(b, 25) ^ c; c -= d;
+            d = rotl32(d, 24) ^ a; a -= b;
+            b = rotl32(b, 20) ^ c; c -= d;
+            d = rotl32(d, 16) ^ a; a -= b;
+        }
     }
     __device__ __forceinline__ void seed(const KeySched &ks, uint32_t substream, uint32_t ctr) {
         a = ks.seed_hi;
@@ -279,6 +319,7 @@ struct Tyche {
         o[0] = next(); o[1] = next(); o[2] = next(); o[3] = next();
     }
 };
+using Tyche = TycheT<false>;
 
 // Key material for a seed.  Host and device: the batched and served kernels
 // build it per request with scalar instructions.
@@ -546,6 +587,8 @@ __device__ __forceinline__ void counter_block(uint32_t blk, uint32_t ctr, const 
         tf4_block<13>(blk, ctr, ks, w);
     } else if constexpr (G == G_TF2X64_13) {
         tf2_block<13>(blk, ctr, ks, w);
+    } else if constexpr (G == G_SQUARES64) {
+        squares64_block(blk, ctr, ks.sqkey, w);
     } else {  // G_SQUARES
         squares_block(blk, ctr, ks.sqkey, w);
     }

@@ -74,10 +74,10 @@ __global__ __launch_bounds__(256) void k_units(UnitArgs a) {
     const uint32_t blk = a.first_block + (g - i * a.bps);
     const uint32_t ctr = a.ctr0 + i;
     uint32_t w[4];
-    if constexpr (G == G_TYCHE) {
+    if constexpr (tyche_like(G)) {
         const uint32_t t = blk / TYCHE_TILE_BLOCKS, l = blk & 63u;
         const uint32_t k = (blk % TYCHE_TILE_BLOCKS) >> 6;
-        Tyche st;
+        TycheT<G == G_TYCHE_I> st;
         st.seed(a.ks, t * 64u + l, ctr);
         for (uint32_t s = 0; s < 4 * k; ++s) st.mix();
         st.next4(w);
@@ -123,6 +123,8 @@ static void *pick_kernel(int gen, int dist, bool units, bool nt) {
     case G_SQUARES: return pick_d<G_SQUARES>(dist, units, nt);
     case G_TF4X32_13: return pick_d<G_TF4X32_13>(dist, units, nt);
     case G_TF2X64_13: return pick_d<G_TF2X64_13>(dist, units, nt);
+    case G_TYCHE_I: return pick_d<G_TYCHE_I>(dist, units, nt);
+    case G_SQUARES64: return pick_d<G_SQUARES64>(dist, units, nt);
     default: return pick_d<G_TYCHE>(dist, units, nt);
     }
 }
@@ -165,7 +167,7 @@ hipError_t launch_fill(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t
     a.ctr0 = ctr0;
     a.delta = delta;
     const Tuned tu = tuned_fill(gen, dist);
-    a.unroll = gen == G_TYCHE ? 64 : (cfg.unroll ? cfg.unroll : tu.unroll);
+    a.unroll = tyche_like(gen) ? 64 : (cfg.unroll ? cfg.unroll : tu.unroll);
     const uint64_t sb = span_blocks(gen, a.unroll);
     a.first_span = first_block / sb;
     a.spans_per_stream = last_block / sb - a.first_span + 1;

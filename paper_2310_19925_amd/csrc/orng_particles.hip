@@ -56,10 +56,10 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs a) {
         if (live) {
             for (uint32_t b = 0; b < nblk; ++b) {
                 uint32_t w[4];
-                if constexpr (G == G_TYCHE) {
+                if constexpr (tyche_like(G)) {
                     // words 4b..4b+3 of the stream: outputs 0..3 of substream b
                     // (the first tile's layout, as in orng_fill)
-                    Tyche st;
+                    TycheT<G == G_TYCHE_I> st;
                     st.seed(ks, b, ctr);
                     st.next4(w);
                 } else {
@@ -93,7 +93,7 @@ using namespace orng;
 extern "C" int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particles,
                                      uint32_t draws, uint32_t ctr0, uint32_t n_iters,
                                      void *d_out, void *stream) {
-    if (gen < ORNG_PHILOX4X32_10 || gen > ORNG_THREEFRY2X64_13 || draws < 1 || draws > 16)
+    if (gen < ORNG_PHILOX4X32_10 || gen > ORNG_SQUARES64 || draws < 1 || draws > 16)
         return ORNG_EINVAL;
     if (n_iters && (uint64_t)ctr0 + n_iters - 1 > 0xFFFFFFFFull) return ORNG_ERANGE;
     if (n_particles && seed0 + (n_particles - 1) < seed0) return ORNG_ERANGE;
@@ -123,6 +123,8 @@ extern "C" int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particl
     case G_SQUARES: kern = ORNG_PK(G_SQUARES); break;
     case G_TF4X32_13: kern = ORNG_PK(G_TF4X32_13); break;
     case G_TF2X64_13: kern = ORNG_PK(G_TF2X64_13); break;
+    case G_TYCHE_I: kern = ORNG_PK(G_TYCHE_I); break;
+    case G_SQUARES64: kern = ORNG_PK(G_SQUARES64); break;
     default: kern = ORNG_PK(G_TYCHE); break;
     }
 #undef ORNG_PK

@@ -84,8 +84,8 @@ __global__ __launch_bounds__(256) void k_range(RangeArgs a) {
         const uint32_t ctr = a.ctr0 + (uint32_t)si;
         int32_t *base = a.out + si * a.n;
         const uint32_t mis = (a.mis + (uint32_t)(si * a.n)) & 3u;
-        if constexpr (G == G_TYCHE) {
-            Tyche st;
+        if constexpr (tyche_like(G)) {
+            TycheT<G == G_TYCHE_I> st;
             st.seed(a.ks, (uint32_t)g * 64u + lane, ctr);
             const uint64_t b0 = g * TYCHE_TILE_BLOCKS;
             for (uint32_t k = 0; k < 64; ++k) {
@@ -122,6 +122,8 @@ static void *range_kernel(int gen) {
     case G_SQUARES: return reinterpret_cast<void *>(&k_range<G_SQUARES>);
     case G_TF4X32_13: return reinterpret_cast<void *>(&k_range<G_TF4X32_13>);
     case G_TF2X64_13: return reinterpret_cast<void *>(&k_range<G_TF2X64_13>);
+    case G_TYCHE_I: return reinterpret_cast<void *>(&k_range<G_TYCHE_I>);
+    case G_SQUARES64: return reinterpret_cast<void *>(&k_range<G_SQUARES64>);
     default: return reinterpret_cast<void *>(&k_range<G_TYCHE>);
     }
 }
@@ -148,7 +150,7 @@ extern "C" int orng_fill_range(int gen, uint64_t seed, uint32_t ctr0, uint32_t n
     a.lo = (uint32_t)lo;
     a.r = (uint32_t)((int64_t)hi - (int64_t)lo);
     a.mis = (uint32_t)((reinterpret_cast<uintptr_t>(d_out) / 4 - offset) & 3u);
-    const uint64_t gs = gen == G_TYCHE ? RANGE_TILE : RANGE_GROUP;
+    const uint64_t gs = tyche_like(gen) ? RANGE_TILE : RANGE_GROUP;
     a.first_group = offset / gs;
     a.groups_per_stream = (offset + per_stream - 1) / gs - a.first_group + 1;
     a.total_groups = a.groups_per_stream * n_streams;

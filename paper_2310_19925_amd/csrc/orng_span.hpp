@@ -132,8 +132,8 @@ __device__ __forceinline__ void process_span(const KeySched &ks, uint32_t ctr, c
     // parallelism (four Box-Muller pairs instead of two; the Threefry4x32
     // normal fill gains ~5% on MI355X).  Emission stays in block order.  Tyche's
     // words come from one sequential state, so it keeps one block per step.
-    if constexpr (G == G_TYCHE) {
-        Tyche st;
+    if constexpr (tyche_like(G)) {
+        TycheT<G == G_TYCHE_I> st;
         st.seed(ks, (uint32_t)span * 64u + lane, ctr);
         const uint64_t tile_block = span * TYCHE_TILE_BLOCKS;
         for (uint32_t k = 0; k < 64; ++k) {
@@ -214,11 +214,14 @@ __device__ __forceinline__ void process_span_any(int gen, int dist, const KeySch
         ORNG_CASE(4, 0) ORNG_CASE(4, 1) ORNG_CASE(4, 2) ORNG_CASE(4, 3)
         ORNG_CASE(5, 0) ORNG_CASE(5, 1) ORNG_CASE(5, 2) ORNG_CASE(5, 3)
         ORNG_CASE(6, 0) ORNG_CASE(6, 1) ORNG_CASE(6, 2) ORNG_CASE(6, 3)
+        ORNG_CASE(7, 0) ORNG_CASE(7, 1) ORNG_CASE(7, 2) ORNG_CASE(7, 3)
+        ORNG_CASE(8, 0) ORNG_CASE(8, 1) ORNG_CASE(8, 2) ORNG_CASE(8, 3)
         default:
             if constexpr (F64N) {
                 switch (gen * NDIST + dist) {
                     ORNG_CASE(0, 4) ORNG_CASE(1, 4) ORNG_CASE(2, 4) ORNG_CASE(3, 4)
-                    ORNG_CASE(4, 4) ORNG_CASE(5, 4) ORNG_CASE(6, 4)
+                    ORNG_CASE(4, 4) ORNG_CASE(5, 4) ORNG_CASE(6, 4) ORNG_CASE(7, 4)
+                    ORNG_CASE(8, 4)
                     default: break;
                 }
             }
@@ -229,7 +232,7 @@ __device__ __forceinline__ void process_span_any(int gen, int dist, const KeySch
 
 // Blocks per span for a generator.
 __host__ __device__ inline uint64_t span_blocks(int gen, uint32_t unroll) {
-    return gen == G_TYCHE ? (uint64_t)TYCHE_TILE_BLOCKS : 64ull * unroll;
+    return tyche_like(gen) ? (uint64_t)TYCHE_TILE_BLOCKS : 64ull * unroll;
 }
 
 }  // namespace orng

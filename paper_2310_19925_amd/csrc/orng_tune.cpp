@@ -69,6 +69,17 @@ static const uint32_t kDefaultTable[NGEN * NDIST][8] = {
         {256, 8, 0, 1, 256, 16, 1, 0},
         {256, 8, 8192, 1, 256, 16, 1, 0},
         {256, 8, 0, 1, 256, 16, 1, 0},
+        // Tyche-i (Tyche's shapes), Squares64 (Squares32's shapes)
+        {64, 64, 0, 2, 512, 1, 1, 0},
+        {64, 64, 0, 2, 512, 1, 1, 0},
+        {256, 64, 0, 1, 128, 1, 1, 0},
+        {512, 64, 0, 2, 128, 1, 1, 8},
+        {256, 64, 0, 1, 128, 1, 1, 0},
+        {64, 4, 0, 1, 256, 8, 1, 0},
+        {64, 8, 0, 1, 256, 8, 1, 0},
+        {256, 2, 8192, 1, 128, 16, 1, 0},
+        {256, 8, 0, 1, 256, 16, 1, 0},
+        {256, 2, 8192, 1, 128, 16, 1, 0},
 };
 
 static Tuned default_tuned(int gen, int dist) {
@@ -121,7 +132,7 @@ static bool sane(const Tuned &t, int gen) {
     return wg_ok(t.wg_size) && wg_ok(t.b_wg_size) && t.unroll >= 1 && t.unroll <= 64 &&
            t.b_unroll >= 1 && t.b_unroll <= 64 && t.b_chunk >= 1 && t.b_chunk <= 64 &&
            t.b_wgs_per_cu <= 64 && t.nontemporal >= 1 &&
-           t.nontemporal <= 2 && (gen != G_TYCHE || t.unroll == 64);
+           t.nontemporal <= 2 && (!tyche_like(gen) || t.unroll == 64);
 }
 
 static int load_locked(const char *path) {
@@ -259,12 +270,12 @@ int orng_autotune(int gen, int dist, const char *cache_path) {
     auto run_fill = [&] { launch_fill(gen, dist, 0x5EED, 0, 1, 0, n, buf, s); };
     for (uint32_t wg : wgs)
         for (uint32_t un : unrolls) {
-            if (gen == G_TYCHE && un != 1) continue;
+            if (tyche_like(gen) && un != 1) continue;
             for (uint32_t cap : caps)
                 for (uint32_t nt = 1; nt <= 2 && e == hipSuccess; ++nt) {
                     Tuned t = best;
                     t.wg_size = wg;
-                    t.unroll = gen == G_TYCHE ? 64 : un;
+                    t.unroll = tyche_like(gen) ? 64 : un;
                     t.max_wgs = cap;
                     t.nontemporal = nt;
                     set_tuned(gen, dist, t);
@@ -307,7 +318,7 @@ int orng_autotune(int gen, int dist, const char *cache_path) {
             for (uint32_t ch : {1u, 4u})
                 for (uint32_t wpc : {0u, 2u, 4u, 8u}) {  // 0: static schedule
                     if (e != hipSuccess) break;
-                    if (gen == G_TYCHE && un != 1) continue;
+                    if (tyche_like(gen) && un != 1) continue;
                     if (wpc == 0 && ch != 1) continue;  // chunk is a queue parameter
                     Tuned t = best;
                     t.b_wg_size = wg;

@@ -67,7 +67,7 @@ def test_header_is_plain_c_and_links(tmp_path):
         '  orng_serve_stats_t st;\n'
         '  (void)r; (void)st;\n'
         '  if (orng_get_launch(&l) != ORNG_OK) return 1;\n'
-        '  if (orng_fill(ORNG_TYCHE + 1, ORNG_U32, 1, 1, 0, 4, (void*)0, (void*)0) != ORNG_EINVAL) return 2;\n'
+        '  if (orng_fill(ORNG_SQUARES64 + 1, ORNG_U32, 1, 1, 0, 4, (void*)0, (void*)0) != ORNG_EINVAL) return 2;\n'
         '  printf("%s %d\\n", orng_strerror(ORNG_ERANGE), orng_version());\n'
         '  return sizeof(orng_req_t) == 48 ? 0 : 3;\n'
         '}\n')

@@ -40,7 +40,7 @@ def _case(R, O, gen, seed, ctr, off, n, pad=0, dist=F64):
 
 
 @pytest.mark.parametrize("dist", F64S)
-@pytest.mark.parametrize("gen", range(7))
+@pytest.mark.parametrize("gen", range(9))
 def test_f64_fill_parity(R, O, gen, dist):
     n = 3 * 8192 + 2 * 517 + 1
     _case(R, O, gen, 0x0123456789ABCDEF, 7, 0, n, dist=dist)
@@ -52,7 +52,7 @@ def test_f64_fill_parity(R, O, gen, dist):
 
 
 @pytest.mark.parametrize("dist", F64S)
-@pytest.mark.parametrize("gen", range(7))
+@pytest.mark.parametrize("gen", range(9))
 def test_f64_fill_multi(R, O, gen, dist):
     for n_streams, off, per in [(1000, 3, 5), (7, 1, 20001)]:
         out = torch.empty(n_streams * per, dtype=torch.int64, device="cuda")
@@ -68,7 +68,7 @@ def test_f64_bulk_sampled(R, O, dist):
     n = 1 << 29
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     rng = np.random.default_rng(12)
-    for gen in range(7):
+    for gen in range(9):
         print("bulk gen=%d dist=%d" % (gen, dist), flush=True)
         R.orng_fill(gen, dist, 0xFEED, 1, 0, n, out)
         torch.cuda.synchronize()
@@ -88,7 +88,7 @@ def _mixed_requests(rng, m, buf_words):
         k = 2 if dist in F64S else 1
         off_words += k - off_words % k  # 8-byte aligned doubles, 4-byte words
         off_words += int(rng.integers(0, 3)) * k
-        rows.append(dict(gen=int(rng.integers(0, 7)), dist=dist,
+        rows.append(dict(gen=int(rng.integers(0, 9)), dist=dist,
                          seed=int(rng.integers(0, 2**63)), ctr=int(rng.integers(0, 2**32)),
                          offset=int(rng.integers(0, 2**32 // k - n)), n=n, at=off_words))
         off_words += n * k
@@ -150,7 +150,7 @@ def test_f64_normal_found_anywhere_in_a_large_batch(R, O):
     buf = torch.full((words,), -1, dtype=torch.int32, device="cuda")
     base = buf.data_ptr()
     dists = [F64N if i == special else (i % 3) for i in range(nreq)]
-    reqs = R.make_requests([i % 7 for i in range(nreq)], dists, [1000 + i for i in range(nreq)],
+    reqs = R.make_requests([i % 9 for i in range(nreq)], dists, [1000 + i for i in range(nreq)],
                            [7] * nreq, [i % 5 for i in range(nreq)], [per] * nreq,
                            base + 8 * per * np.arange(nreq))
     for fn in (R.orng_fill_batched, R.orng_fill_each):
@@ -160,5 +160,5 @@ def test_f64_normal_found_anywhere_in_a_large_batch(R, O):
         host = buf.cpu().numpy().view(np.uint32).reshape(nreq, 2 * per)
         for i in [0, 1, 2, special - 1, special, special + 1, nreq - 1]:
             k = 2 if dists[i] in F64S else 1
-            ref = O.fill(i % 7, dists[i], 1000 + i, 7, i % 5, per)
+            ref = O.fill(i % 9, dists[i], 1000 + i, 7, i % 5, per)
             assert np.array_equal(host[i, :per * k], np.ascontiguousarray(ref).view(np.uint32)), i

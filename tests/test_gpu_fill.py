@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-GENS = range(7)
+GENS = range(9)
 DISTS = range(3)
 
 
@@ -80,7 +80,7 @@ def test_fill_tiny_and_edges(R, O, gen):
 def test_fill_errors(R):
     out = torch.empty(16, dtype=torch.int32, device="cuda")
     with pytest.raises(R.OrngError) as e:
-        R.orng_fill(7, 0, 1, 1, 0, 4, out)
+        R.orng_fill(9, 0, 1, 1, 0, 4, out)
     assert e.value.status == R.EINVAL
     with pytest.raises(R.OrngError) as e:
         R.orng_fill(0, 5, 1, 1, 0, 4, out)

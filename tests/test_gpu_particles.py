@@ -27,7 +27,7 @@ def _run(R, gen, seed0, P, D, ctr0, T):
     return host[:-1]
 
 
-@pytest.mark.parametrize("gen", range(7))
+@pytest.mark.parametrize("gen", range(9))
 @pytest.mark.parametrize("draws", [1, 3, 4, 7, 16])
 def test_particle_streams_parity(R, O, gen, draws):
     P, T = 1000, 9
@@ -36,7 +36,7 @@ def test_particle_streams_parity(R, O, gen, draws):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("gen", range(7))
+@pytest.mark.parametrize("gen", range(9))
 def test_particle_streams_paper_shape_sampled(R, O, gen):
     P, D, T = 16000, 3, 2000
     got = _run(R, gen, 1, P, D, 1, T).reshape(T, P, D)

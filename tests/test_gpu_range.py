@@ -36,7 +36,7 @@ def _case(R, O, gen, seed, ctr, off, n, lo, hi, pad=0, n_streams=1):
     assert np.all(host[:pad] == -7) and np.all(host[pad + total:] == -7)
 
 
-@pytest.mark.parametrize("gen", range(7))
+@pytest.mark.parametrize("gen", range(9))
 def test_range_fill_parity(R, O, gen):
     n = 3 * 8192 + 2 * 517 + 1  # several Tyche tiles and counter groups, ragged tail
     for k, (lo, hi) in enumerate(RANGES):
@@ -49,7 +49,7 @@ def test_range_fill_parity(R, O, gen):
         _case(R, O, gen, 5, 6, off, cnt, -50, 50)
 
 
-@pytest.mark.parametrize("gen", range(7))
+@pytest.mark.parametrize("gen", range(9))
 def test_range_fill_multi(R, O, gen):
     for n_streams, off, per in [(1000, 3, 5), (7, 1, 20001), (4, 0, 256)]:
         _case(R, O, gen, 11, 100, off, per, -(2**20), 2**20, n_streams=n_streams)
@@ -61,7 +61,7 @@ def test_range_bulk_sampled(R, O):
     lo, hi = -(10**9), 10**9 + 7
     out = torch.empty(n, dtype=torch.int32, device="cuda")
     rng = np.random.default_rng(21)
-    for gen in range(7):
+    for gen in range(9):
         print("bulk gen=%d" % gen, flush=True)
         R.orng_fill_range(gen, 0xFEED, 1, 1, 0, n, lo, hi, out)
         torch.cuda.synchronize()

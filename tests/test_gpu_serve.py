@@ -33,7 +33,7 @@ def _random_reqs(rng, m, lo=10, hi=16):
     out = []
     for _ in range(m):
         n = int(2 ** (lo + (hi - lo) * rng.random()))
-        out.append(dict(gen=int(rng.integers(0, 7)), dist=int(rng.integers(0, 3)),
+        out.append(dict(gen=int(rng.integers(0, 9)), dist=int(rng.integers(0, 3)),
                         seed=int(rng.integers(0, 2**63)), ctr=int(rng.integers(0, 2**32)),
                         offset=int(rng.integers(0, 2**32 - n)), n=n))
     return out

@@ -56,7 +56,7 @@ def test_fill_multi_validation(L):
     assert L.orng_fill_multi(0, 0, 1, 2**32 - 3, 3, 2**32 - 1, 2, FAKE, None) == ERANGE
     assert L.orng_fill_multi(0, 0, 1, 0, 0, 0, 4, None, None) == 0
     assert L.orng_fill_multi(0, 0, 1, 0, 5, 0, 0, None, None) == 0
-    assert L.orng_fill_multi(7, 0, 1, 0, 5, 0, 4, FAKE, None) == EINVAL
+    assert L.orng_fill_multi(9, 0, 1, 0, 5, 0, 4, FAKE, None) == EINVAL
     assert L.orng_fill_multi(0, 3, 1, 0, 2, 2**31 - 1, 2, FAKE, None) == ERANGE
     assert L.orng_fill_multi(0, 3, 1, 0, 2, 0, 2, FAKE + 4, None) == EINVAL
 
@@ -88,7 +88,7 @@ def test_bd2_validation(L):
 
 
 def test_particle_streams_validation(L):
-    assert L.orng_particle_streams(7, 0, 10, 3, 0, 1, FAKE, None) == EINVAL
+    assert L.orng_particle_streams(9, 0, 10, 3, 0, 1, FAKE, None) == EINVAL
     assert L.orng_particle_streams(0, 0, 10, 0, 0, 1, FAKE, None) == EINVAL
     assert L.orng_particle_streams(0, 0, 10, 17, 0, 1, FAKE, None) == EINVAL
     assert L.orng_particle_streams(0, 0, 10, 3, 2**32 - 1, 2, FAKE, None) == ERANGE
@@ -118,7 +118,7 @@ def _reqs(rows):
 def test_batched_validation_rejects_whole_batch(L, fn):
     f = getattr(L, fn)
     cases = [
-        ([(0, 0, 0, 16, FAKE, 0), (7, 0, 0, 16, FAKE, 0)], EINVAL),     # bad generator
+        ([(0, 0, 0, 16, FAKE, 0), (9, 0, 0, 16, FAKE, 0)], EINVAL),     # bad generator
         ([(0, 5, 0, 16, FAKE, 0)], EINVAL),                              # bad distribution
         ([(0, 0, 0, 16, FAKE, 1)], EINVAL),                              # reserved flags
         ([(0, 0, 2**32 - 8, 16, FAKE, 0)], ERANGE),                      # past the period
@@ -180,7 +180,7 @@ def test_tune_table_loader(L, tmp_path):
     good = tmp_path / "good.txt"
     good.write_text("# header\n0 0 256 2 0 2 256 4 1 0\n4 1 256 64 0 2 256 1 1 0\n")
     assert L.orng_tune_load(str(good).encode()) == 0
-    assert L.orng_autotune(7, 0, None) == EINVAL
+    assert L.orng_autotune(9, 0, None) == EINVAL
     assert L.orng_autotune(0, 5, None) == EINVAL
 
 
@@ -200,7 +200,7 @@ def test_serve_create_validation(L):
 
 
 def test_fill_range_validation(L):
-    assert L.orng_fill_range(7, 0, 0, 1, 0, 4, 0, 10, FAKE, None) == EINVAL
+    assert L.orng_fill_range(9, 0, 0, 1, 0, 4, 0, 10, FAKE, None) == EINVAL
     assert L.orng_fill_range(-1, 0, 0, 1, 0, 4, 0, 10, FAKE, None) == EINVAL
     assert L.orng_fill_range(0, 0, 0, 1, 0, 4, 10, 10, FAKE, None) == EINVAL
     assert L.orng_fill_range(0, 0, 0, 1, 0, 4, 11, 10, FAKE, None) == EINVAL
