@@ -37,12 +37,12 @@ static const uint32_t kDefaultTable[NGEN * NDIST][8] = {
         {64, 4, 0, 1, 512, 8, 1, 0},
         {512, 2, 8192, 1, 128, 16, 1, 0},
         {64, 4, 0, 2, 512, 8, 1, 0},
-        {512, 2, 8192, 1, 128, 16, 1, 0},
+        {512, 8, 8192, 1, 256, 16, 1, 4},
         {256, 8, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 2, 128, 16, 1, 0},
         {512, 8, 8192, 1, 256, 16, 1, 0},
-        {512, 8, 8192, 2, 128, 16, 1, 0},
+        {256, 8, 0, 1, 128, 16, 1, 8},
         {512, 4, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 1, 128, 16, 1, 0},
         {512, 4, 8192, 2, 128, 16, 1, 0},
@@ -63,23 +63,23 @@ static const uint32_t kDefaultTable[NGEN * NDIST][8] = {
         {512, 4, 8192, 1, 128, 16, 1, 0},
         {512, 2, 8192, 1, 128, 16, 1, 0},
         {512, 8, 8192, 1, 256, 16, 1, 0},
-        {512, 2, 8192, 1, 128, 16, 1, 0},
+        {512, 4, 8192, 1, 256, 16, 1, 0},
         {256, 8, 0, 2, 256, 8, 1, 0},
         {512, 8, 8192, 1, 128, 16, 1, 0},
         {256, 8, 0, 1, 256, 16, 1, 0},
         {256, 8, 8192, 1, 256, 16, 1, 0},
-        {256, 8, 0, 1, 256, 16, 1, 0},
-        // Tyche-i (Tyche's shapes), Squares64 (Squares32's shapes)
+        {256, 8, 0, 1, 256, 16, 1, 4},
+        // Tyche-i, Squares64 (started from Tyche's and Squares32's shapes)
         {64, 64, 0, 2, 512, 1, 1, 0},
         {64, 64, 0, 2, 512, 1, 1, 0},
         {256, 64, 0, 1, 128, 1, 1, 0},
-        {512, 64, 0, 2, 128, 1, 1, 8},
+        {64, 64, 0, 2, 128, 1, 1, 8},
         {256, 64, 0, 1, 128, 1, 1, 0},
         {64, 4, 0, 1, 256, 8, 1, 0},
-        {64, 8, 0, 1, 256, 8, 1, 0},
+        {64, 4, 0, 2, 512, 8, 1, 0},
         {256, 2, 8192, 1, 128, 16, 1, 0},
-        {256, 8, 0, 1, 256, 16, 1, 0},
-        {256, 2, 8192, 1, 128, 16, 1, 0},
+        {64, 4, 0, 1, 512, 8, 1, 0},
+        {512, 4, 8192, 1, 256, 16, 1, 0},
 };
 
 static Tuned default_tuned(int gen, int dist) {
