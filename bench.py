@@ -97,18 +97,21 @@ def roofs(gen, dist, n, ms):
 # calibration factors a 1 GiB device copy gives for each counter.  Valid only
 # for the kernel sources and launch table they were measured on: bench.py
 # reports null traffic when the hash of those sources differs.
-TRAFFIC_SRC_SHA = "0b67a570d0fd0a85"
-TRAFFIC_FACTORS = (1.9999218017636564, 1.0)  # FETCH, WRITE
+TRAFFIC_SRC_SHA = "daf7df28b068c05d"
+TRAFFIC_FACTORS = (1.9999156033845427, 1.0)  # FETCH, WRITE
 TRAFFIC_KIB = {
-    (0, 0): (87.75, 4194304.0), (0, 1): (52.25, 4194575.625), (0, 2): (86.6875, 4194321.5), (0, 3): (49.5, 4194304.0),
-    (0, 4): (64.5, 4194305.5), (1, 0): (53.6875, 4194307.5), (1, 1): (65.4375, 4194316.625), (1, 2): (63.4375, 4194304.0),
-    (1, 3): (57.0, 4194318.5), (1, 4): (69.5, 4194304.0), (2, 0): (55.5, 4194323.625), (2, 1): (53.0, 4194322.125),
-    (2, 2): (62.5, 4194304.0), (2, 3): (57.5, 4194322.5), (2, 4): (71.0, 4194304.0), (3, 0): (52.0, 4194304.125),
-    (3, 1): (38.0, 4194338.0), (3, 2): (105.75, 4194319.25), (3, 3): (53.0, 4195531.875), (3, 4): (66.5, 4194321.125),
-    (4, 0): (40.1875, 4194304.0), (4, 1): (32.1875, 4194304.0), (4, 2): (41.4375, 4194324.5), (4, 3): (67.0625, 4194304.0),
-    (4, 4): (40.125, 4194320.75), (5, 0): (47.0, 4194332.875), (5, 1): (54.0, 4194389.0), (5, 2): (62.5, 4194359.25),
-    (5, 3): (53.0, 4196751.5), (5, 4): (64.5, 4194308.625), (6, 0): (51.0, 4194304.0), (6, 1): (46.0, 4194840.625),
-    (6, 2): (53.5, 4194342.875), (6, 3): (48.5, 4195149.75), (6, 4): (69.0, 4194306.75),
+    (0, 0): (80.375, 4194304.0), (0, 1): (50.8125, 4194478.125), (0, 2): (85.75, 4194336.125), (0, 3): (49.0, 4194304.0),
+    (0, 4): (59.5, 4194317.75), (1, 0): (58.0, 4194306.75), (1, 1): (50.5625, 4194315.25), (1, 2): (67.5, 4194304.0),
+    (1, 3): (49.5, 4194316.25), (1, 4): (72.0, 4194304.0), (2, 0): (57.0, 4194319.375), (2, 1): (55.5, 4194305.75),
+    (2, 2): (63.5625, 4194304.0), (2, 3): (56.0, 4194329.625), (2, 4): (69.5, 4194304.0), (3, 0): (42.5, 4194316.125),
+    (3, 1): (54.0, 4194336.625), (3, 2): (89.625, 4194308.0), (3, 3): (53.0, 4195013.875), (3, 4): (66.0, 4194315.375),
+    (4, 0): (43.1875, 4194304.0), (4, 1): (34.875, 4194304.0), (4, 2): (43.75, 4194334.125), (4, 3): (63.625, 4194304.0),
+    (4, 4): (40.5625, 4194319.0), (5, 0): (45.5, 4195950.125), (5, 1): (50.5, 4195313.875), (5, 2): (63.5, 4194329.625),
+    (5, 3): (53.5, 4194912.5), (5, 4): (67.0, 4194306.125), (6, 0): (49.5, 4194304.0), (6, 1): (52.0, 4197809.25),
+    (6, 2): (58.5, 4194304.0), (6, 3): (54.0, 4195242.125), (6, 4): (63.0, 4194305.875), (7, 0): (31.5625, 4194304.0),
+    (7, 1): (25.0, 4194304.0), (7, 2): (33.0, 4194347.625), (7, 3): (25.0, 4194304.0), (7, 4): (36.5, 4194324.0),
+    (8, 0): (49.5, 4196268.0), (8, 1): (48.0, 4194304.0), (8, 2): (50.5, 4194304.0), (8, 3): (35.5, 4196169.875),
+    (8, 4): (57.5, 4194317.875),
 }
 
 
