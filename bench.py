@@ -444,8 +444,8 @@ def main():
     ap.add_argument("--only", default="", help="gen:dist list to restrict the fills (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the generation path needs no communication "
-              "and this build runs on a single MI355X (--gpus %d refused)" % args.gpus,
+        print("bench.py measures one GPU only: every stream is generated where it is used, "
+              "with no communication between GPUs (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
