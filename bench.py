@@ -157,7 +157,7 @@ def cpu_baseline(seed, target_s=15.0):
         for d in range(3):
             O.fill(g, d, seed, 0, 0, per, nthreads=th)
     t_small = time.perf_counter() - t0
-    scale = max(1, min(256, int(target_s / max(t_small, 1e-3))))
+    scale = max(1, min(1024, int(target_s / max(t_small, 1e-3))))  # at most the whole 2^30
     per = per * scale
     buf_u = np.empty(per, np.uint32)
     t0 = time.perf_counter()
