@@ -474,6 +474,20 @@ constexpr double F64_LN2_LO = 0x1.9ef35793c7673p-41;
 constexpr double F64_SQRT2 = 0x1.6a09e667f3bcdp+0;
 constexpr double F64_TWO_PI_2M53 = 0x1.921fb54442d18p-51;  // float64(2 pi) * 2^-53
 
+// One float64 fused multiply-add as one VOP3 instruction (a*b + c, rounded
+// once, as fma()), with the addend (a series coefficient) in a scalar register
+// pair.  Written out because with fma() the compiler keeps every coefficient
+// in vector registers and, per Horner step, copies it into the destination of
+// the two-address form (v_fmac_f64): 80-90 VGPRs and a move per step.  With
+// scalar addends the float64 normal fills need 47-59 VGPRs and run 5-11%
+// faster on MI355X (the compiler rematerialises or spills the constants to
+// vector lanes; results are the same bits).
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
 __device__ __forceinline__ double ln_u1_f64(uint64_t K) {
     // K <= 2^53, so its float64 value is exact; frexp splits it exactly
     const double Kd = fma((double)(uint32_t)(K >> 32), 0x1p32, (double)(uint32_t)K);
@@ -486,15 +500,15 @@ __device__ __forceinline__ double ln_u1_f64(uint64_t K) {
     const double s = (m - 1.0) / (m + 1.0);
     const double z = s * s;
     double P = 1.0 / 21.0;
-    P = fma(P, z, 1.0 / 19.0);
-    P = fma(P, z, 1.0 / 17.0);
-    P = fma(P, z, 1.0 / 15.0);
-    P = fma(P, z, 1.0 / 13.0);
-    P = fma(P, z, 1.0 / 11.0);
-    P = fma(P, z, 1.0 / 9.0);
-    P = fma(P, z, 1.0 / 7.0);
-    P = fma(P, z, 1.0 / 5.0);
-    P = fma(P, z, 1.0 / 3.0);
+    P = fma3(P, z, 1.0 / 19.0);
+    P = fma3(P, z, 1.0 / 17.0);
+    P = fma3(P, z, 1.0 / 15.0);
+    P = fma3(P, z, 1.0 / 13.0);
+    P = fma3(P, z, 1.0 / 11.0);
+    P = fma3(P, z, 1.0 / 9.0);
+    P = fma3(P, z, 1.0 / 7.0);
+    P = fma3(P, z, 1.0 / 5.0);
+    P = fma3(P, z, 1.0 / 3.0);
     const double t = 2.0 * s;
     const double ln_m = fma(t, z * P, t);
     const double E = (double)(e - 53);
@@ -507,24 +521,24 @@ __device__ __forceinline__ void sincos_turn_f64(uint64_t k, double &c, double &s
     const double x = (double)r * F64_TWO_PI_2M53;
     const double z = x * x;
     double S = -1.0 / 121645100408832000.0;
-    S = fma(S, z, 1.0 / 355687428096000.0);
-    S = fma(S, z, -1.0 / 1307674368000.0);
-    S = fma(S, z, 1.0 / 6227020800.0);
-    S = fma(S, z, -1.0 / 39916800.0);
-    S = fma(S, z, 1.0 / 362880.0);
-    S = fma(S, z, -1.0 / 5040.0);
-    S = fma(S, z, 1.0 / 120.0);
-    S = fma(S, z, -1.0 / 6.0);
+    S = fma3(S, z, 1.0 / 355687428096000.0);
+    S = fma3(S, z, -1.0 / 1307674368000.0);
+    S = fma3(S, z, 1.0 / 6227020800.0);
+    S = fma3(S, z, -1.0 / 39916800.0);
+    S = fma3(S, z, 1.0 / 362880.0);
+    S = fma3(S, z, -1.0 / 5040.0);
+    S = fma3(S, z, 1.0 / 120.0);
+    S = fma3(S, z, -1.0 / 6.0);
     const double sn = fma(x * z, S, x);
     double C = 1.0 / 6402373705728000.0;
-    C = fma(C, z, -1.0 / 20922789888000.0);
-    C = fma(C, z, 1.0 / 87178291200.0);
-    C = fma(C, z, -1.0 / 479001600.0);
-    C = fma(C, z, 1.0 / 3628800.0);
-    C = fma(C, z, -1.0 / 40320.0);
-    C = fma(C, z, 1.0 / 720.0);
-    C = fma(C, z, -1.0 / 24.0);
-    C = fma(C, z, 1.0 / 2.0);
+    C = fma3(C, z, -1.0 / 20922789888000.0);
+    C = fma3(C, z, 1.0 / 87178291200.0);
+    C = fma3(C, z, -1.0 / 479001600.0);
+    C = fma3(C, z, 1.0 / 3628800.0);
+    C = fma3(C, z, -1.0 / 40320.0);
+    C = fma3(C, z, 1.0 / 720.0);
+    C = fma3(C, z, -1.0 / 24.0);
+    C = fma3(C, z, 1.0 / 2.0);
     const double cs = fma(-z, C, 1.0);
     const uint32_t q = (uint32_t)j & 3u;
     const double cr = (q & 1u) ? sn : cs;
