@@ -97,21 +97,21 @@ def roofs(gen, dist, n, ms):
 # calibration factors a 1 GiB device copy gives for each counter.  Valid only
 # for the kernel sources and launch table they were measured on: bench.py
 # reports null traffic when the hash of those sources differs.
-TRAFFIC_SRC_SHA = "608421ce2de9450c"
-TRAFFIC_FACTORS = (1.9999239473653783, 1.0)  # FETCH, WRITE
+TRAFFIC_SRC_SHA = "7c45a135ad260bf3"
+TRAFFIC_FACTORS = (1.999922278563641, 1.0)  # FETCH, WRITE
 TRAFFIC_KIB = {
-    (0, 0): (79.5625, 4194304.0), (0, 1): (50.5, 4194757.125), (0, 2): (79.625, 4194326.25), (0, 3): (49.0, 4194304.0),
-    (0, 4): (70.5, 4194312.0), (1, 0): (54.375, 4194309.0), (1, 1): (59.5625, 4194315.625), (1, 2): (63.875, 4194304.0),
-    (1, 3): (51.5, 4194313.0), (1, 4): (75.0, 4194304.625), (2, 0): (55.5, 4194339.75), (2, 1): (59.0625, 4194311.5),
-    (2, 2): (63.5625, 4194304.0), (2, 3): (55.0, 4194348.625), (2, 4): (82.875, 4194304.0), (3, 0): (51.5, 4194327.75),
-    (3, 1): (45.0625, 4194398.125), (3, 2): (105.75, 4194309.125), (3, 3): (53.0, 4196748.625), (3, 4): (73.5, 4194327.25),
-    (4, 0): (37.6875, 4194304.0), (4, 1): (31.0, 4194304.0), (4, 2): (39.3125, 4194451.625), (4, 3): (65.625, 4194304.0),
-    (4, 4): (40.5, 4194330.5), (5, 0): (43.0, 4195499.75), (5, 1): (54.0, 4196190.125), (5, 2): (59.0, 4194323.5),
-    (5, 3): (50.0, 4196677.0), (5, 4): (69.5, 4194306.25), (6, 0): (53.0, 4194304.0), (6, 1): (50.0, 4197436.75),
-    (6, 2): (57.5, 4194312.5), (6, 3): (51.5, 4196577.5), (6, 4): (76.5, 4194318.625), (7, 0): (25.0, 4194304.0),
-    (7, 1): (29.0, 4194304.0), (7, 2): (36.5, 4194368.125), (7, 3): (29.5, 4194304.0), (7, 4): (43.625, 4194350.0),
-    (8, 0): (48.0, 4196417.0), (8, 1): (50.5, 4194304.0), (8, 2): (54.5, 4194435.375), (8, 3): (49.0, 4196550.375),
-    (8, 4): (68.0, 4194315.75),
+    (0, 0): (80.75, 4194304.0), (0, 1): (50.5, 4194321.25), (0, 2): (83.75, 4194327.125), (0, 3): (49.0, 4194304.0),
+    (0, 4): (70.5, 4194331.75), (1, 0): (54.0, 4194318.5), (1, 1): (59.25, 4194328.75), (1, 2): (63.875, 4194304.0),
+    (1, 3): (51.5, 4194324.125), (1, 4): (75.0, 4194304.125), (2, 0): (55.5, 4194318.125), (2, 1): (59.25, 4194354.5),
+    (2, 2): (63.75, 4194304.0), (2, 3): (55.0, 4194307.0), (2, 4): (82.1875, 4194304.0), (3, 0): (51.5, 4194304.0),
+    (3, 1): (45.0, 4194304.0), (3, 2): (106.1875, 4194329.375), (3, 3): (53.0, 4195101.25), (3, 4): (73.5, 4194321.875),
+    (4, 0): (38.6875, 4194304.0), (4, 1): (30.6875, 4194304.0), (4, 2): (38.125, 4194304.0), (4, 3): (66.6875, 4194304.0),
+    (4, 4): (40.5, 4194351.375), (5, 0): (43.0, 4194547.25), (5, 1): (54.0, 4194324.375), (5, 2): (59.0, 4194353.125),
+    (5, 3): (50.0, 4194913.0), (5, 4): (69.5, 4194312.125), (6, 0): (53.0, 4194304.0), (6, 1): (50.0, 4195179.875),
+    (6, 2): (57.5, 4194378.125), (6, 3): (51.5, 4195270.375), (6, 4): (76.5, 4194310.625), (7, 0): (25.0, 4194304.0),
+    (7, 1): (29.0, 4194304.0), (7, 2): (36.5, 4194386.5), (7, 3): (29.5, 4194304.0), (7, 4): (43.5, 4194304.0),
+    (8, 0): (48.0, 4197750.25), (8, 1): (50.5, 4194304.0), (8, 2): (54.5, 4194376.375), (8, 3): (49.0, 4195111.375),
+    (8, 4): (68.0, 4194329.625),
 }
 
 

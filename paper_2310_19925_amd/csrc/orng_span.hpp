@@ -183,14 +183,9 @@ __device__ __forceinline__ void process_span(const KeySched &ks, uint32_t ctr, c
 }
 
 // Workgroups are dealt to the 8 XCDs of the device round-robin (workgroup b
-// runs on XCD b mod 8).  For grids whose tiles share lookup data with their
-// neighbours, map workgroup b to tile (b mod 8) * (G / 8) + b / 8 so that each
-// XCD (and its L2) owns one contiguous eighth of the tiles.  G must be a
-// multiple of 8; the map is a bijection on [0, G).
+// runs on XCD b mod 8); the batched and served launchers round their grids to
+// a multiple of this.
 constexpr uint32_t XCDS = 8;
-__device__ __forceinline__ uint64_t xcd_tile(uint64_t b, uint64_t grid) {
-    return (b % XCDS) * (grid / XCDS) + b / XCDS;
-}
 
 // Runtime (gen, dist) dispatch for kernels whose requests mix generators.
 // F64N selects whether the float64 normal cases are compiled in: their code
