@@ -190,8 +190,8 @@ def _time_events(stream, fn, reps):
 
 def bench_plain_multi(orng, inputs, stream, dev):
     """The configured plain multi-stream fill: one seed (42), 2^20 streams
-    (counters 0..2^20-1) of 4 words each, u32 and float32 uniform; one
-    launch, so microseconds."""
+    (counters 0..2^20-1) of 4 words each, u32 and float32 uniform (and the
+    same streams as 4 integers each); one launch, so microseconds."""
     import torch
     ns, per = inputs.PLAIN_STREAMS, inputs.PLAIN_PER_STREAM
     n = ns * per
@@ -201,6 +201,10 @@ def bench_plain_multi(orng, inputs, stream, dev):
         ms = _time_events(stream, lambda: orng.orng_fill_multi(0, d, inputs.PLAIN_SEED, 0, ns, 0,
                                                                per, out, stream), 21)
         res[name] = {"us": round(ms * 1e3, 2), "gsamples_s": round(n / (ms * 1e-3) / 1e9, 2)}
+    # the same streams as integers in [lo, hi) (two words per sample)
+    ms = _time_events(stream, lambda: orng.orng_fill_range(0, inputs.PLAIN_SEED, 0, ns, 0, per,
+                                                           RANGE_LO, RANGE_HI, out, stream), 21)
+    res["i32_range"] = {"us": round(ms * 1e3, 2), "gsamples_s": round(n / (ms * 1e-3) / 1e9, 2)}
     del out
     return res
 

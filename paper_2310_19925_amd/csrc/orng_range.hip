@@ -20,7 +20,9 @@
 // instruction).  Groups are numbered in absolute sample space, so a fill that
 // starts mid-group masks the samples in front of its first one; samples at the
 // range ends, and outputs not aligned with the store width, are written one
-// word at a time.
+// word at a time.  Many streams of a few samples each (under 64 units per
+// stream) take one lane per (stream, unit) instead, so a wave is not spent on
+// one stream's handful of samples.
 #include "../../include/orng.h"
 #include "orng_device.hpp"
 #include "orng_internal.hpp"
@@ -114,6 +116,64 @@ __global__ __launch_bounds__(256) void k_range(RangeArgs a) {
     }
 }
 
+// Many short streams: one lane per (stream, unit).  Counter generators: unit
+// u is blocks 2u and 2u+1 (samples 4u..4u+3); Tyche: unit u is block u
+// (samples 2u, 2u+1), reached by seeding its substream and stepping it to
+// the block.  Samples outside [s0, s0 + n) are not written.
+struct RangeUnitArgs {
+    KeySched ks;
+    int32_t *out;
+    uint64_t s0, n;
+    uint32_t first_unit, units_per_stream, total_units;
+    uint32_t ctr0, lo, r;
+};
+
+template <int G>
+__global__ __launch_bounds__(256) void k_range_units(RangeUnitArgs a) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.total_units) return;
+    const uint32_t i = g / a.units_per_stream;
+    const uint32_t u = a.first_unit + (g - i * a.units_per_stream);
+    const uint32_t ctr = a.ctr0 + i;
+    int32_t *base = a.out + (uint64_t)i * a.n;
+    const uint64_t send = a.s0 + a.n;
+    if constexpr (tyche_like(G)) {
+        const uint32_t t = u / TYCHE_TILE_BLOCKS, l = u & 63u;
+        const uint32_t k = (u % TYCHE_TILE_BLOCKS) >> 6;
+        TycheT<G == G_TYCHE_I> st;
+        st.seed(a.ks, t * 64u + l, ctr);
+        for (uint32_t j = 0; j < 4 * k; ++j) st.mix();
+        uint32_t w[4];
+        st.next4(w);
+        const uint32_t v[2] = {a.lo + range_scale(w[0], w[1], a.r),
+                               a.lo + range_scale(w[2], w[3], a.r)};
+        range_store<2>(base, 2 * (uint64_t)u, a.s0, send, false, v);
+    } else {
+        uint32_t w[4], x[4];
+        counter_block<G>(2 * u, ctr, a.ks, w);
+        counter_block<G>(2 * u + 1, ctr, a.ks, x);
+        const uint32_t v[4] = {a.lo + range_scale(w[0], w[1], a.r),
+                               a.lo + range_scale(w[2], w[3], a.r),
+                               a.lo + range_scale(x[0], x[1], a.r),
+                               a.lo + range_scale(x[2], x[3], a.r)};
+        range_store<4>(base, 4 * (uint64_t)u, a.s0, send, false, v);
+    }
+}
+
+static void *range_units_kernel(int gen) {
+    switch (gen) {
+    case G_PHILOX: return reinterpret_cast<void *>(&k_range_units<G_PHILOX>);
+    case G_TF4X32: return reinterpret_cast<void *>(&k_range_units<G_TF4X32>);
+    case G_TF2X64: return reinterpret_cast<void *>(&k_range_units<G_TF2X64>);
+    case G_SQUARES: return reinterpret_cast<void *>(&k_range_units<G_SQUARES>);
+    case G_TF4X32_13: return reinterpret_cast<void *>(&k_range_units<G_TF4X32_13>);
+    case G_TF2X64_13: return reinterpret_cast<void *>(&k_range_units<G_TF2X64_13>);
+    case G_TYCHE_I: return reinterpret_cast<void *>(&k_range_units<G_TYCHE_I>);
+    case G_SQUARES64: return reinterpret_cast<void *>(&k_range_units<G_SQUARES64>);
+    default: return reinterpret_cast<void *>(&k_range_units<G_TYCHE>);
+    }
+}
+
 static void *range_kernel(int gen) {
     switch (gen) {
     case G_PHILOX: return reinterpret_cast<void *>(&k_range<G_PHILOX>);
@@ -141,6 +201,31 @@ extern "C" int orng_fill_range(int gen, uint64_t seed, uint32_t ctr0, uint32_t n
     if (n_streams && (uint64_t)ctr0 + n_streams - 1 > 0xFFFFFFFFull) return ORNG_ERANGE;
     if (n_streams == 0 || per_stream == 0) return ORNG_OK;
     if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 3u)) return ORNG_EINVAL;
+    // many streams of a few samples each: one lane per unit (see k_range_units)
+    const uint64_t spu = tyche_like(gen) ? 2 : 4;  // samples per unit
+    const uint64_t fu = offset / spu, lu = (offset + per_stream - 1) / spu;
+    if (n_streams > 1 && lu - fu + 1 < 64 && (uint64_t)n_streams * (lu - fu + 1) < (1ull << 31)) {
+        RangeUnitArgs u;
+        u.ks = make_keysched(seed);
+        u.out = d_out;
+        u.s0 = offset;
+        u.n = per_stream;
+        u.first_unit = (uint32_t)fu;
+        u.units_per_stream = (uint32_t)(lu - fu + 1);
+        u.total_units = (uint32_t)(n_streams * (lu - fu + 1));
+        u.ctr0 = ctr0;
+        u.lo = (uint32_t)lo;
+        u.r = (uint32_t)((int64_t)hi - (int64_t)lo);
+        void *uargs[] = {&u};
+        const hipError_t e = hipLaunchKernel(range_units_kernel(gen),
+                                             dim3((u.total_units + 255) / 256), dim3(256), uargs,
+                                             0, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) {
+            set_hip_error(e);
+            return ORNG_EHIP;
+        }
+        return ORNG_OK;
+    }
     RangeArgs a;
     a.ks = make_keysched(seed);
     a.out = d_out;

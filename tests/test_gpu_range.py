@@ -55,6 +55,16 @@ def test_range_fill_multi(R, O, gen):
         _case(R, O, gen, 11, 100, off, per, -(2**20), 2**20, n_streams=n_streams)
 
 
+@pytest.mark.parametrize("gen", range(9))
+def test_range_many_short_streams(R, O, gen):
+    """Short streams go one lane per unit: every generator, offsets inside a
+    unit, and Tyche blocks deep inside a tile (offset 5000 is block 2500)."""
+    for n_streams, off, per in [(20000, 3, 5), (3000, 5000, 7), (257, 0, 1), (64, 1, 126),
+                                (2, 8191, 2)]:
+        _case(R, O, gen, 0xABC, 77, off, per, -3, 4, n_streams=n_streams)
+    _case(R, O, gen, 0xABC, 77, 2, 9, -10, 10, pad=1, n_streams=500)
+
+
 def test_range_bulk_sampled(R, O):
     """2^30 samples (4 GiB) from one stream, checked on sampled positions."""
     n = 1 << 30
