@@ -145,9 +145,11 @@ def cpu_threads():
     return max(1, min(n, 16))
 
 
-def cpu_baseline(seed, target_s=15.0):
+def cpu_baseline(seed, target_s=30.0):
     """Oracle (test infrastructure, untuned) on the host cores: the same 15
-    fills on a bounded sample of each, scaled to GSamples/s."""
+    fills on a bounded sample of each, scaled to GSamples/s.  The sample is
+    sized from a 2^20-sample trial run; the trial's fixed costs make the
+    estimate about twice the real time, so target_s = 30 gives ~10-15 s."""
     import numpy as np
     from oracle import oracle as O
     th = cpu_threads()
