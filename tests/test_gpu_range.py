@@ -65,6 +65,27 @@ def test_range_many_short_streams(R, O, gen):
     _case(R, O, gen, 0xABC, 77, 2, 9, -10, 10, pad=1, n_streams=500)
 
 
+def test_range_plain_multistream_config(R, O):
+    """The bench's multi-stream line: 2^20 streams (counters 0..2^20-1) of 4
+    integers each from seed 42, one launch; sampled streams against the
+    oracle, every stream in range."""
+    from paper_2310_19925_amd import inputs
+    ns, per = inputs.PLAIN_STREAMS, inputs.PLAIN_PER_STREAM
+    lo, hi = -(10**9), 10**9 + 7
+    out = torch.empty(ns * per, dtype=torch.int32, device="cuda")
+    for gen in (0, 3, 4):
+        print("plain multi gen=%d" % gen, flush=True)
+        R.orng_fill_range(gen, inputs.PLAIN_SEED, 0, ns, 0, per, lo, hi, out)
+        torch.cuda.synchronize()
+        host = out.cpu().numpy().reshape(ns, per)
+        assert host.min() >= lo and host.max() < hi
+        rng = np.random.default_rng(23)
+        for i in np.unique(np.concatenate([[0, 1, ns - 1], rng.integers(0, ns, 300)])):
+            ref = O.fill_range(gen, inputs.PLAIN_SEED, int(i), 1, 0, per, lo, hi)
+            assert np.array_equal(host[i], ref), (gen, i)
+    del out
+
+
 def test_range_bulk_sampled(R, O):
     """2^30 samples (4 GiB) from one stream, checked on sampled positions."""
     n = 1 << 30
