@@ -6,8 +6,9 @@
 //
 // Host: requests are validated, each is cut into tiles of W consecutive spans
 // (a span is the fill kernels' unit: 64*U blocks of four words, or one Tyche
-// tile; W = waves per workgroup), and a prefix sum gives every request its
-// first tile number.  The header, the request table
+// tile; W = waves per workgroup, taken with the rest of the launch shape from
+// the (generator, distribution) pair holding most of the batch's words), and
+// a prefix sum gives every request its first tile number.  The header, the request table
 // and a tile -> request map are written into pinned staging and uploaded with
 // two copies into a device buffer whose layout is fixed for its capacity.
 // Device: a persistent grid pulls tiles from an atomic cursor in the header
@@ -41,7 +42,7 @@ struct DevReq {             // 64 bytes, read by the kernel with scalar loads
     uint32_t ctr;
     uint32_t unroll;        // blocks per lane per tile (counter generators)
     uint32_t flags;         // gen | dist << 4 | delta << 8
-    uint32_t pad;
+    uint32_t tiles;         // number of the request's tiles
 };
 static_assert(sizeof(DevReq) == 64, "DevReq layout");
 
@@ -331,59 +332,96 @@ static bool use_graphs() {
     return on;
 }
 
+// Table row of one request; `ts` is its first tile, `cnt` its tile count.
+static void make_row(DevReq &d, const orng_req_t &r, uint32_t unroll, uint64_t first_span,
+                     uint64_t ts, uint64_t cnt) {
+    const uint64_t kw = words_per_sample((int)r.dist);
+    d.out = static_cast<char *>(r.out);
+    d.p0 = r.offset * kw;  // positions and counts in stream words from here on
+    d.n = r.n * kw;
+    d.seed = r.seed;
+    d.first_span = first_span;
+    d.tile_start = ts;
+    d.ctr = r.ctr;
+    d.unroll = unroll;
+    const uint64_t addr_words = reinterpret_cast<uintptr_t>(r.out) / 4;
+    const uint32_t delta = (uint32_t)((addr_words - d.p0) & 3u);
+    d.flags = r.gen | (r.dist << 4) | (delta << 8);
+    d.tiles = (uint32_t)cnt;
+}
+
+// The (generator, distribution) pair holding most of a batch's words picks the
+// batch's launch shape (workgroup size, so the tile size, and the schedule);
+// ties go to the lower pair number.
+static int dominant_pair(const uint64_t *words) {
+    int best = 0;
+    for (int k = 1; k < NGEN * NDIST; ++k)
+        if (words[k] > words[best]) best = k;
+    return best;
+}
+
+static void unroll_table(uint32_t unroll_of[NGEN][NDIST]) {
+    for (int g = 0; g < NGEN; ++g)
+        for (int d = 0; d < NDIST; ++d)
+            unroll_of[g][d] = tyche_like(g) ? 64 : tuned_fill(g, d).b_unroll;
+}
+
 int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     if (nreq && !reqs) return ORNG_EINVAL;
     if (!nreq) return ORNG_OK;
     if (nreq > 0xFFFFFFFFull) return ORNG_ENOMEM;  // the tile map holds 32-bit request numbers
-    // Host preparation in two parallel passes over contiguous ranges of the
-    // request list: (1) validate and tile every request, summing each range's
-    // tiles; then, after a scan over the ranges, (2) write each request's
-    // table row and its tiles' entries of the tile map.  Every request keeps
-    // its own row (one without work owns no tiles).
+    // Host preparation in three parallel passes over contiguous ranges of the
+    // request list: (1) validate every request and count the words of each
+    // (generator, distribution) pair, which picks the launch shape; (2) tile
+    // every request, summing each range's tiles; then, after a scan over the
+    // ranges, (3) write each request's table row and its tiles' entries of
+    // the tile map.  Every request keeps its own row (one without work owns no
+    // tiles).
     const Ranges rg(nreq);
-    std::unique_ptr<uint64_t[]> fspan(new uint64_t[nreq]), cnt(new uint64_t[nreq]);
-    std::unique_ptr<uint32_t[]> unr(new uint32_t[nreq]);
-    std::vector<uint64_t> range_tiles(rg.T + 1, 0);
+    constexpr int NP = NGEN * NDIST;
+    std::vector<uint64_t> range_words(rg.T * NP, 0);
     std::vector<size_t> range_bad(rg.T, nreq);  // first invalid request of each range
     std::vector<int> range_st(rg.T, ORNG_OK);
-    std::vector<char> range_f64n(rg.T, 0);  // a float64 normal request with work
-    uint32_t unroll_of[NGEN][NDIST];  // one table lookup per pair, not per request
-    for (int g = 0; g < NGEN; ++g)
-        for (int d = 0; d < NDIST; ++d)
-            unroll_of[g][d] = tyche_like(g) ? 64 : tuned_fill(g, d).b_unroll;
-    // The workgroup shape, and so the tile size, follows the first request
-    // with work; this pass finds it before tiling.
-    size_t first_live = nreq;
-    for (size_t i = 0; i < nreq && first_live == nreq; ++i)
-        if (reqs[i].n && validate_request(reqs[i]) == ORNG_OK) first_live = i;
-    const uint32_t W =
-        first_live < nreq ? batch_wg((int)reqs[first_live].gen, (int)reqs[first_live].dist) / 64
-                          : 1;
     rg.run([&](size_t t, size_t a, size_t b) {
-        uint64_t sum = 0;
+        uint64_t *w = &range_words[t * NP];
         for (size_t i = a; i < b; ++i) {
             const int st = validate_request(reqs[i]);
             if (st != ORNG_OK) { range_bad[t] = i; range_st[t] = st; return; }
+            w[reqs[i].gen * NDIST + reqs[i].dist] += reqs[i].n * words_per_sample((int)reqs[i].dist);
+        }
+    });
+    for (size_t t = 0; t < rg.T; ++t)
+        if (range_bad[t] < nreq) return range_st[t];  // ranges are in list order
+    uint64_t words[NP] = {0};
+    for (size_t t = 0; t < rg.T; ++t)
+        for (int k = 0; k < NP; ++k) words[k] += range_words[t * NP + k];
+    const bool f64n = [&] {
+        for (int g = 0; g < NGEN; ++g)
+            if (words[g * NDIST + ORNG_F64_NORMAL]) return true;
+        return false;
+    }();
+    const int pair = dominant_pair(words);
+    const uint32_t W = batch_wg(pair / NDIST, pair % NDIST) / 64;
+    uint32_t unroll_of[NGEN][NDIST];  // one table lookup per pair, not per request
+    unroll_table(unroll_of);
+
+    std::unique_ptr<uint64_t[]> fspan(new uint64_t[nreq]), cnt(new uint64_t[nreq]);
+    std::vector<uint64_t> range_tiles(rg.T + 1, 0);
+    rg.run([&](size_t t, size_t a, size_t b) {
+        uint64_t sum = 0;
+        for (size_t i = a; i < b; ++i) {
             cnt[i] = 0;
             fspan[i] = 0;
-            unr[i] = 0;
             if (!reqs[i].n) continue;
-            unr[i] = unroll_of[reqs[i].gen][reqs[i].dist];
-            if (reqs[i].dist == ORNG_F64_NORMAL) range_f64n[t] = 1;
-            request_tiles(reqs[i], unr[i], W, &fspan[i], &cnt[i]);
+            request_tiles(reqs[i], unroll_of[reqs[i].gen][reqs[i].dist], W, &fspan[i], &cnt[i]);
             sum += cnt[i];
         }
         range_tiles[t + 1] = sum;
     });
-    for (size_t t = 0; t < rg.T; ++t)
-        if (range_bad[t] < nreq) return range_st[t];  // ranges are in list order
     for (size_t t = 0; t < rg.T; ++t) range_tiles[t + 1] += range_tiles[t];
-    bool f64n = false;
-    for (size_t t = 0; t < rg.T; ++t) f64n = f64n || range_f64n[t];
     const uint64_t tiles = range_tiles[rg.T];
     if (tiles == 0) return ORNG_OK;
     if (tiles > (1ull << 28)) return ORNG_ENOMEM;
-    const orng_req_t &r0 = reqs[first_live];
 
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -398,7 +436,7 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     ORNG_TRY(ensure_capacity(c, nreq, tiles));
     if (!db->capture) ORNG_TRY(hipStreamCreateWithFlags(&db->capture, hipStreamNonBlocking));
 
-    const BatchShape sh = batch_shape((int)r0.gen, (int)r0.dist, tiles);
+    const BatchShape sh = batch_shape(pair / NDIST, pair % NDIST, tiles);
     size_t map_off;
     layout_bytes(c.cap_req, c.cap_tiles, &map_off);
     BatchHdr *hdr = reinterpret_cast<BatchHdr *>(c.h_buf);
@@ -414,20 +452,7 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
         uint64_t ts = range_tiles[t];
         for (size_t i = a; i < b; ++i) {
             const orng_req_t &r = reqs[i];
-            const uint64_t kw = words_per_sample((int)r.dist);
-            DevReq &d = dq[i];
-            d.out = static_cast<char *>(r.out);
-            d.p0 = r.offset * kw;  // positions and counts in stream words from here on
-            d.n = r.n * kw;
-            d.seed = r.seed;
-            d.first_span = fspan[i];
-            d.tile_start = ts;
-            d.ctr = r.ctr;
-            d.unroll = unr[i];
-            const uint64_t addr_words = reinterpret_cast<uintptr_t>(r.out) / 4;
-            const uint32_t delta = (uint32_t)((addr_words - d.p0) & 3u);
-            d.flags = r.gen | (r.dist << 4) | (delta << 8);
-            d.pad = 0;
+            make_row(dq[i], r, r.n ? unroll_of[r.gen][r.dist] : 0, fspan[i], ts, cnt[i]);
             std::fill_n(map + ts, cnt[i], (uint32_t)i);
             ts += cnt[i];
         }
