@@ -247,6 +247,30 @@ typedef struct {
 int orng_fill_batched(const orng_req_t *h_reqs, size_t nreq, void *stream);
 
 /*
+ * orng_fill_batched_noalloc -- orng_fill_batched for callers that cannot
+ * allocate memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same results, the same generation kernels, and
+ * no allocation of any kind by the call.  The batch's header, request table
+ * (64 bytes per request) and tile map (4 bytes per tile) live in a fixed
+ * device array of the library (about 24 MiB, held by every device the call
+ * runs on until the process ends), and the rows are staged in a fixed host
+ * array.  Limits: at most ORNG_NOALLOC_MAX_REQUESTS requests and
+ * ORNG_NOALLOC_MAX_TILES tiles (a tile is 2,048 to 65,536 words at the
+ * built-in launch shapes; any request with work needs at least one).
+ * Behaviour: the call returns after the request rows are uploaded, which
+ * waits for work queued earlier on `stream`; the kernels then run on `stream`
+ * without a captured graph.  Every call on a device shares that device's
+ * array, which keeps the last call's contents: calls on one stream run one
+ * after the other; calls that overlap on one device (other streams, other
+ * host threads' streams) race and must not be made.
+ * Errors: EINVAL / ERANGE as orng_fill_batched for the first bad request;
+ *         ENOMEM if nreq > ORNG_NOALLOC_MAX_REQUESTS or the batch needs more
+ *         than ORNG_NOALLOC_MAX_TILES tiles (nothing is enqueued then).
+ */
+enum { ORNG_NOALLOC_MAX_REQUESTS = 131072, ORNG_NOALLOC_MAX_TILES = 4194304 };
+int orng_fill_batched_noalloc(const orng_req_t *h_reqs, size_t nreq, void *stream);
+
+/*
  * orng_fill_each -- the plain path for the same request list: one fill launch
  * per request, in order (the baseline the batched and served paths are
  * compared with).  Same results and errors as orng_fill_batched.

@@ -493,12 +493,125 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     return ORNG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free variant of fill_batched
+// ---------------------------------------------------------------------------
+// For callers that cannot allocate: the batch's header, request table and tile
+// map live in `scratch`, a device array of fixed size defined here, instead of
+// a buffer the library allocates.  Host code never passes the array's name to
+// a kernel or a copy (in host code it is a host-side stand-in, not a device
+// address): the address is looked up once per device with
+// hipGetSymbolAddress, while that device is current, and only that address is
+// used.  The host writes the header and the request rows in one serial pass
+// into a static host array; the upload from that pageable array is done before
+// hipMemcpyAsync returns, so the array is free again when the call returns.  A
+// small kernel then writes the tile map from the rows, and the generation
+// kernel is the one orng_fill_batched runs (launched directly, no graph).
+// Every call on a device shares its scratch: calls on one stream follow each
+// other in stream order; calls that overlap on one device race.
+constexpr uint64_t NOALLOC_ROWS_END =
+    sizeof(BatchHdr) + (uint64_t)ORNG_NOALLOC_MAX_REQUESTS * sizeof(DevReq);
+constexpr uint64_t NOALLOC_MAP_OFF = (NOALLOC_ROWS_END + 255) / 256 * 256;
+constexpr uint64_t NOALLOC_BYTES =
+    NOALLOC_MAP_OFF + (uint64_t)ORNG_NOALLOC_MAX_TILES * sizeof(uint32_t);
+
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+static std::mutex g_na_mu;                        // one allocation-free call at a time per process
+alignas(64) static char g_na_stage[NOALLOC_ROWS_END];  // host: header + request rows
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static char *g_na_ptr[NOALLOC_MAX_DEVICES];       // device address of `scratch`, per device
+
+// Tile map from the request rows: wave r writes the entries of request r.
+__global__ __launch_bounds__(256) void k_tile_map(const DevReq *reqs, uint32_t nreq,
+                                                  uint32_t *map) {
+    const uint32_t r = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (r >= nreq) return;
+    const uint64_t t0 = reqs[r].tile_start;
+    const uint32_t cnt = reqs[r].tiles;
+    for (uint32_t k = threadIdx.x & 63u; k < cnt; k += 64u) map[t0 + k] = r;
+}
+
+int fill_batched_noalloc(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
+    if (nreq && !reqs) return ORNG_EINVAL;
+    if (!nreq) return ORNG_OK;
+    constexpr int NP = NGEN * NDIST;
+    uint64_t words[NP] = {0};
+    for (size_t i = 0; i < nreq; ++i) {
+        const int st = validate_request(reqs[i]);
+        if (st != ORNG_OK) return st;
+        words[reqs[i].gen * NDIST + reqs[i].dist] += reqs[i].n * words_per_sample((int)reqs[i].dist);
+    }
+    if (nreq > ORNG_NOALLOC_MAX_REQUESTS) return ORNG_ENOMEM;
+    bool f64n = false;
+    for (int g = 0; g < NGEN; ++g) f64n = f64n || words[g * NDIST + ORNG_F64_NORMAL] != 0;
+    const int pair = dominant_pair(words);
+    const uint32_t W = batch_wg(pair / NDIST, pair % NDIST) / 64;
+    uint32_t unroll_of[NGEN][NDIST];
+    unroll_table(unroll_of);
+
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    DevReq *rows = reinterpret_cast<DevReq *>(g_na_stage + sizeof(BatchHdr));
+    uint64_t tiles = 0;
+    for (size_t i = 0; i < nreq; ++i) {
+        const orng_req_t &r = reqs[i];
+        uint64_t fs = 0, cnt = 0;
+        if (r.n) request_tiles(r, unroll_of[r.gen][r.dist], W, &fs, &cnt);
+        if (cnt > ORNG_NOALLOC_MAX_TILES - tiles) return ORNG_ENOMEM;
+        make_row(rows[i], r, r.n ? unroll_of[r.gen][r.dist] : 0, fs, tiles, cnt);
+        tiles += cnt;
+    }
+    if (tiles == 0) return ORNG_OK;
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; }
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return ORNG_ENOMEM;
+    if (!g_na_ptr[dev]) {  // set-up, once per device, with that device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) { set_hip_error(e); return ORNG_EHIP; }
+        g_na_ptr[dev] = static_cast<char *>(p);
+    }
+    char *base = g_na_ptr[dev];
+
+    const BatchShape sh = batch_shape(pair / NDIST, pair % NDIST, tiles);
+    BatchHdr *hdr = reinterpret_cast<BatchHdr *>(g_na_stage);
+    std::memset(hdr, 0, sizeof(BatchHdr));
+    hdr->total_tiles = tiles;
+    hdr->cursor = 0;  // the work queue starts empty on every call
+    hdr->nreq = (uint32_t)nreq;
+    hdr->chunk = sh.chunk;
+    hdr->spans_per_tile = W;
+#define ORNG_TRY(x) do { e = (x); if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; } } while (0)
+    ORNG_TRY(hipMemcpyAsync(base, g_na_stage, sizeof(BatchHdr) + nreq * sizeof(DevReq),
+                            hipMemcpyHostToDevice, stream));
+    BatchView v;
+    v.hdr = reinterpret_cast<BatchHdr *>(base);
+    v.reqs = reinterpret_cast<const DevReq *>(base + sizeof(BatchHdr));
+    v.map = reinterpret_cast<const uint32_t *>(base + NOALLOC_MAP_OFF);
+    uint32_t *map = reinterpret_cast<uint32_t *>(base + NOALLOC_MAP_OFF);
+    const uint32_t nr = (uint32_t)nreq;
+    void *margs[] = {&v.reqs, const_cast<uint32_t *>(&nr), &map};
+    ORNG_TRY(hipLaunchKernel(reinterpret_cast<void *>(&k_tile_map), dim3((nr + 3) / 4), dim3(256),
+                             margs, 0, stream));
+    void *args[] = {&v};
+    ORNG_TRY(hipLaunchKernel(batched_kernel(sh, f64n), dim3(sh.grid), dim3(sh.wg), args, 0,
+                             stream));
+#undef ORNG_TRY
+    return ORNG_OK;
+}
+
 }  // namespace orng
 
 extern "C" {
 
 int orng_fill_batched(const orng_req_t *h_reqs, size_t nreq, void *stream) {
     return orng::fill_batched(h_reqs, nreq, static_cast<hipStream_t>(stream));
+}
+
+int orng_fill_batched_noalloc(const orng_req_t *h_reqs, size_t nreq, void *stream) {
+    return orng::fill_batched_noalloc(h_reqs, nreq, static_cast<hipStream_t>(stream));
 }
 
 int orng_fill_each(const orng_req_t *h_reqs, size_t nreq, void *stream) {

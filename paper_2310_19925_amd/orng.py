@@ -76,6 +76,7 @@ def _load():
         "orng_particle_streams": [i32, u64, u32, u32, u32, u32, vp, vp],
         "orng_normal_pairs": [vp, vp, u64, vp, vp, vp],
         "orng_fill_batched": [vp, C.c_size_t, vp],
+        "orng_fill_batched_noalloc": [vp, C.c_size_t, vp],
         "orng_fill_each": [vp, C.c_size_t, vp],
         "orng_autotune": [i32, i32, C.c_char_p],
         "orng_tune_load": [C.c_char_p],
@@ -211,6 +212,17 @@ def orng_fill_batched(reqs, stream=None):
     assert reqs.dtype.itemsize == 48 and reqs.flags["C_CONTIGUOUS"]
     _check(_lib.orng_fill_batched(reqs.ctypes.data if reqs.size else None, reqs.size,
                                   _stream(stream)), "orng_fill_batched")
+
+
+def orng_fill_batched_noalloc(reqs, stream=None):
+    """As orng_fill_batched, with the batch tables in the library's fixed
+    device array (no allocation; see include/orng.h for the limits)."""
+    assert reqs.dtype.itemsize == 48 and reqs.flags["C_CONTIGUOUS"]
+    _check(_lib.orng_fill_batched_noalloc(reqs.ctypes.data if reqs.size else None, reqs.size,
+                                          _stream(stream)), "orng_fill_batched_noalloc")
+
+
+NOALLOC_MAX_REQUESTS, NOALLOC_MAX_TILES = 131072, 4194304
 
 
 def orng_fill_each(reqs, stream=None):

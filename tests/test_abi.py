@@ -79,3 +79,31 @@ def test_header_is_plain_c_and_links(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, (r.returncode, r.stderr)
     assert r.stdout.startswith("position or counter out of range")
+
+
+def test_noalloc_batched_limits_without_gpu():
+    """orng_fill_batched_noalloc checks its requests and its fixed limits on
+    the host, before any device call: too many requests or tiles give ENOMEM,
+    a bad request its own error, an empty batch OK."""
+    import numpy as np
+    lib = ctypes.CDLL(LIB)
+    fn = lib.orng_fill_batched_noalloc
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    fn.restype = ctypes.c_int
+    dt = np.dtype([("seed", "<u8"), ("offset", "<u8"), ("n", "<u8"), ("out", "<u8"),
+                   ("ctr", "<u4"), ("gen", "<u4"), ("dist", "<u4"), ("flags", "<u4")])
+    max_req, max_tiles = 131072, 4194304
+    hdr = open(os.path.join(ROOT, "include", "orng.h")).read()
+    assert "ORNG_NOALLOC_MAX_REQUESTS = %d" % max_req in hdr
+    assert "ORNG_NOALLOC_MAX_TILES = %d" % max_tiles in hdr
+    r = np.zeros(max_req + 1, dt)
+    assert fn(r.ctypes.data, r.size, None) == -3          # ENOMEM: too many requests
+    assert fn(r.ctypes.data, max_req, None) == 0          # all empty: nothing to do
+    r = np.zeros(max_req, dt)
+    r["n"], r["out"] = 1 << 20, 1 << 20                   # 64 tiles or more each
+    assert fn(r.ctypes.data, r.size, None) == -3          # ENOMEM: too many tiles
+    r[5]["gen"] = 10
+    assert fn(r.ctypes.data, r.size, None) == -1          # the bad request comes first
+    r = np.zeros(3, dt)
+    r[1]["offset"], r[1]["n"], r[1]["out"] = 2**32 - 2, 4, 4096
+    assert fn(r.ctypes.data, r.size, None) == -2          # ERANGE
