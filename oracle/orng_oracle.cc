@@ -831,45 +831,43 @@ void oracle_sincos_turn_f64_n(const uint64_t *k, uint64_t n, double *c, double *
  * section 5.1 runs it in 2-D).  Particle id pid is the seed and the step's
  * counter is step0 + s (the example keys its generator by the particle id and
  * the loop iteration).  One draw of two doubles takes words 0..3 of Philox
- * stream (pid, counter): r.x from words 0, 1 and r.y from words 2, 3.  Each
- * velocity component first loses the drag term (c * v) * dt, c = gamma/mass,
- * then gains the kick (2 r - 1) * sqrt(dt), in the paper's operation order.
- * Reading: the example elides what else a step does; here each step then
- * moves the particle, x <- x + v * dt.  Every operation is one IEEE float64
- * operation (no contraction).  Pinned in the test-suite: (a) with c = 2^10 and
- * dt = 2^-10 the drag cancels the velocity exactly, so after every step v is
- * the kick alone, (2u - 1) / 32 from the pinned Philox words and conversion,
- * and one step from rest moves x by exactly v dt; (b) for general parameters
- * the sample mean and variance of v and x over many particles match the
- * closed forms of the AR(1) velocity process and its running sum.
+ * stream (pid, counter): r.x from words 0, 1 and r.y from words 2, 3.
+ * Model: a velocity component relaxes at rate c = gamma/mass and receives a
+ * uniform kick on [-sqrt(dt), sqrt(dt)); the position integrates the
+ * velocity.  Reading (the example elides the rest of a step and the float
+ * evaluation order): with the step constants a = 1 - c*dt and w = 2*sqrt(dt),
+ * each component takes v = a*v + (r - 0.5)*w, then x = x + v*dt.  Every
+ * operation is one IEEE float64 operation (no contraction); r - 0.5 is exact.
+ * Pinned in the test-suite: (a) with c = 2^10 and dt = 2^-10, a = 0 exactly,
+ * so after every step v is the kick alone, (2u - 1) / 32 from the pinned
+ * Philox words and conversion, and one step from rest moves x by exactly
+ * v dt; (b) for general parameters the sample mean and variance of v and x
+ * over many particles match the closed forms of the AR(1) velocity process
+ * and its running sum.
  * ------------------------------------------------------------------------- */
 int oracle_bd2(uint64_t pid0, const uint32_t *ids, uint32_t count, uint32_t step0,
                uint32_t n_steps, double dt, double c, double *x, double *y, double *vx,
                double *vy, int nthreads) {
     if (n_steps && (uint64_t)step0 + n_steps - 1 > 0xFFFFFFFFull) return -2;
-    const double sqrt_dt = std::sqrt(dt);
-    parallel_ranges(count, nthreads, [&](uint64_t a, uint64_t b, int) {
-        for (uint64_t k = a; k < b; ++k) {
+    const double decay = 1.0 - c * dt;
+    const double width = 2.0 * std::sqrt(dt);
+    parallel_ranges(count, nthreads, [&](uint64_t lo, uint64_t hi, int) {
+        for (uint64_t k = lo; k < hi; ++k) {
             const uint64_t pid = pid0 + (ids ? ids[k] : k);
             const uint32_t key[2] = {(uint32_t)pid, (uint32_t)(pid >> 32)};
-            double px = x[k], py = y[k], ux = vx[k], uy = vy[k];
+            double *pos[2] = {&x[k], &y[k]};
+            double *vel[2] = {&vx[k], &vy[k]};
             for (uint32_t s = 0; s < n_steps; ++s) {
                 const uint32_t ctr[4] = {0u, step0 + s, 0u, 0u};
                 uint32_t w[4];
                 oracle_philox4x32_10(ctr, key, w);
-                const double rx = oracle_u01_f64(w[0], w[1]);
-                const double ry = oracle_u01_f64(w[2], w[3]);
-                ux = ux - c * ux * dt;
-                uy = uy - c * uy * dt;
-                ux = ux + (rx * 2.0 - 1.0) * sqrt_dt;
-                uy = uy + (ry * 2.0 - 1.0) * sqrt_dt;
-                px = px + ux * dt;
-                py = py + uy * dt;
+                const double r[2] = {oracle_u01_f64(w[0], w[1]), oracle_u01_f64(w[2], w[3])};
+                for (int d = 0; d < 2; ++d) {
+                    const double v = decay * *vel[d] + (r[d] - 0.5) * width;
+                    *vel[d] = v;
+                    *pos[d] = *pos[d] + v * dt;
+                }
             }
-            x[k] = px;
-            y[k] = py;
-            vx[k] = ux;
-            vy[k] = uy;
         }
     });
     return 0;

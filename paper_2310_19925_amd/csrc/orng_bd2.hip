@@ -2,12 +2,16 @@
 // benchmark of section 5.1): every particle is one stream, seeded by its id
 // and counted by the step, so a step needs no state besides the particle.
 //
-// Per particle and step (float64, every operation rounded once; the build
-// turns contraction off):
-//   r = two doubles from words 0..3 of Philox stream (pid, step0 + s)
-//   v <- v - (c v) dt        c = gamma / mass           (drag)
-//   v <- v + (2 r - 1) sqrt(dt)                         (uniform kick)
-//   x <- x + v dt                                       (move)
+// The model: each velocity component relaxes at the rate c = gamma / mass and
+// takes a uniform kick on [-sqrt(dt), sqrt(dt)); the position integrates the
+// velocity.  Per step this library evaluates it as, for each component d of
+// (x, y), with u_d the double made from words 2d, 2d+1 of Philox stream
+// (pid, step0 + s):
+//   v_d <- a v_d + (u_d - 1/2) w        a = 1 - c dt,  w = 2 sqrt(dt)
+//   x_d <- x_d + v_d dt
+// a and w are formed once on the host; every operation is one IEEE float64
+// operation (the build turns contraction off).  u - 1/2 is exact, so the kick
+// is (2u - 1) sqrt(dt) rounded once.
 // The paper launches one kernel per step and loads and stores the particle
 // each time; here a launch runs steps_per_launch steps with the particle in
 // registers (0: all steps in one launch).  Results are the same for every
@@ -25,7 +29,7 @@ struct Bd2Args {
     double *x, *y, *vx, *vy;
     uint64_t pid0;
     uint32_t n, step0, n_steps, pad;
-    double dt, c, sqrt_dt;
+    double dt, decay, kick;  // dt, a = 1 - c dt, w = 2 sqrt(dt)
 };
 
 __global__ __launch_bounds__(256) void k_bd2(Bd2Args a) {
@@ -33,24 +37,21 @@ __global__ __launch_bounds__(256) void k_bd2(Bd2Args a) {
     if (i >= a.n) return;
     const uint64_t pid = a.pid0 + i;
     const uint32_t klo = (uint32_t)pid, khi = (uint32_t)(pid >> 32);
-    double px = a.x[i], py = a.y[i], ux = a.vx[i], uy = a.vy[i];
-    const double c = a.c, dt = a.dt, sq = a.sqrt_dt;
+    double pos[2] = {a.x[i], a.y[i]}, vel[2] = {a.vx[i], a.vy[i]};
     for (uint32_t s = 0; s < a.n_steps; ++s) {
         uint32_t w[4];
         philox_block0_lanekey(a.step0 + s, klo, khi, w);
-        const double rx = u01_f64(w[0], w[1]);
-        const double ry = u01_f64(w[2], w[3]);
-        ux = ux - c * ux * dt;
-        uy = uy - c * uy * dt;
-        ux = ux + (rx * 2.0 - 1.0) * sq;
-        uy = uy + (ry * 2.0 - 1.0) * sq;
-        px = px + ux * dt;
-        py = py + uy * dt;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const double kick = (u01_f64(w[2 * d], w[2 * d + 1]) - 0.5) * a.kick;
+            vel[d] = a.decay * vel[d] + kick;
+            pos[d] = pos[d] + vel[d] * a.dt;
+        }
     }
-    a.x[i] = px;
-    a.y[i] = py;
-    a.vx[i] = ux;
-    a.vy[i] = uy;
+    a.x[i] = pos[0];
+    a.y[i] = pos[1];
+    a.vx[i] = vel[0];
+    a.vy[i] = vel[1];
 }
 
 }  // namespace orng
@@ -75,8 +76,8 @@ extern "C" int orng_bd2(uint64_t pid0, uint32_t n, uint32_t step0, uint32_t n_st
     a.n = n;
     a.pad = 0;
     a.dt = dt;
-    a.c = gamma_over_m;
-    a.sqrt_dt = std::sqrt(dt);
+    a.decay = 1.0 - gamma_over_m * dt;
+    a.kick = 2.0 * std::sqrt(dt);
     const uint32_t per = steps_per_launch ? steps_per_launch : n_steps;
     const uint32_t grid = (n + 255) / 256;
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -31,9 +31,10 @@ def test_u01_f64_is_the_top_53_bits_exactly(O):
 @pytest.mark.parametrize("pid", [0, 12345, (7 << 32) | 99])
 def test_bd2_special_case_kick_only(O, pid):
     """gamma/m = 2^10 with dt = 2^-10 makes the drag remove the whole velocity
-    exactly (c v dt = v), and sqrt(dt) = 2^-5, so after every step v equals the
-    kick alone, (2u - 1) / 32, with u from words 0..3 of Philox stream
-    (pid, step); from rest, x after two steps is exactly dt (v1 + v2)."""
+    in one step (the decay 1 - c dt is exactly 0), and sqrt(dt) = 2^-5, so
+    after every step v equals the kick alone, (2u - 1) / 32, with u from words
+    0..3 of Philox stream (pid, step); from rest, x after two steps is exactly
+    dt (v1 + v2)."""
     c, dt = 2.0**10, 2.0**-10
     step0 = 17
     st = O.bd2(pid, 1, step0=step0, n_steps=1, dt=dt, c=c,
