@@ -185,11 +185,13 @@ int orng_brownian(uint64_t seed, uint32_t ctr0, uint32_t n_particles, uint32_t d
  * seed; step s (s < n_steps) uses counter step0 + s.  Per step, with r.x from
  * words 0, 1 and r.y from words 2, 3 of Philox4x32-10 stream (pid, step0 + s),
  * each word pair (w0, w1) read as the double ((w1 << 32 | w0) >> 11) * 2^-53
- * in [0, 1):
- *   v <- v - (gamma_over_m * v) * dt
- *   v <- v + (2 r - 1) * sqrt(dt)
+ * in [0, 1): the velocity relaxes at the rate gamma_over_m and takes a
+ * uniform kick on [-sqrt(dt), sqrt(dt)), and the position integrates it,
+ * evaluated for both components as
+ *   v <- a * v + (r - 0.5) * w        a = 1 - gamma_over_m * dt, w = 2 sqrt(dt)
  *   x <- x + v * dt
- * for both components, every operation one IEEE float64 operation.
+ * with a and w formed once per call and every operation one IEEE float64
+ * operation (r - 0.5 is exact).
  * d_x, d_y, d_vx, d_vy: device float64 arrays of n entries (SoA), read and
  *   written in place; 8-byte aligned, not overlapping.
  * steps_per_launch: steps run per kernel launch with the particle kept in
@@ -303,6 +305,14 @@ int orng_tune_load(const char *cache_path);
  * steps are in flight, so requests that arrive while others run join the next
  * step and their work overlaps on the device.  Results are bit-identical to
  * orng_fill of the same request, alone or in any mix.
+ * Failures: if a step cannot be enqueued (an upload or launch error on the
+ * host), the steps already queued are waited for and the requests they finish
+ * end done; every other unfinished request ends with that error (its poll or
+ * wait returns it, e.g. ORNG_EHIP), later submits return it, and
+ * orng_serve_destroy returns it after freeing the server.  A device fault ends
+ * every unfinished request at once.  For tests of this path, the environment
+ * variable ORNG_SERVE_FAIL_STEP=k (read by orng_serve_create) makes the k-th
+ * step of the server fail that way.
  * ------------------------------------------------------------------------- */
 typedef struct orng_server orng_server_t;
 
@@ -344,6 +354,12 @@ int orng_serve_create(const orng_serve_cfg_t *cfg, orng_server_t **srv);
    caller's buffer is written.  Errors: EINVAL/ERANGE (as orng_fill), ENOMEM
    (output larger than the arena), EBUSY (server shutting down). */
 int orng_serve_submit(orng_server_t *srv, const orng_req_t *req, uint64_t *ticket);
+/* Non-blocking submit: the request is queued only if the server can admit it
+   at once (no request waits ahead of it, a device slot is free and, when
+   req->out == NULL, its arena range is free; the range is taken by this
+   call).  Otherwise nothing is queued and ORNG_EAGAIN is returned.  Other
+   errors as orng_serve_submit. */
+int orng_serve_try_submit(orng_server_t *srv, const orng_req_t *req, uint64_t *ticket);
 /* Queue n requests in one call (one arrival of many); tickets[i] receives the
    ticket of reqs[i].  All requests are validated first: on an error nothing is
    queued and the status is that of the first bad request. */

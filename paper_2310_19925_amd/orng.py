@@ -82,6 +82,7 @@ def _load():
         "orng_tune_load": [C.c_char_p],
         "orng_serve_create": [C.POINTER(orng_serve_cfg_t), C.POINTER(C.c_void_p)],
         "orng_serve_submit": [vp, C.POINTER(orng_req_t), C.POINTER(C.c_uint64)],
+        "orng_serve_try_submit": [vp, C.POINTER(orng_req_t), C.POINTER(C.c_uint64)],
         "orng_serve_submit_many": [vp, vp, C.c_size_t, vp],
         "orng_serve_release_many": [vp, vp, C.c_size_t, C.c_int64, C.POINTER(C.c_size_t)],
         "orng_serve_poll": [vp, u64, C.POINTER(orng_result_t)],
@@ -251,6 +252,18 @@ def orng_serve_submit(srv, gen, dist, seed, ctr, offset, n, out=None):
     r = orng_req_t(seed, offset, n, _ptr(out), ctr, gen, dist, 0)
     t = C.c_uint64()
     _check(_lib.orng_serve_submit(srv, C.byref(r), C.byref(t)), "orng_serve_submit")
+    return t.value
+
+
+def orng_serve_try_submit(srv, gen, dist, seed, ctr, offset, n, out=None):
+    """Non-blocking submit: the ticket, or None when the server cannot admit
+    the request at once (ORNG_EAGAIN; nothing was queued)."""
+    r = orng_req_t(seed, offset, n, _ptr(out), ctr, gen, dist, 0)
+    t = C.c_uint64()
+    st = _lib.orng_serve_try_submit(srv, C.byref(r), C.byref(t))
+    if st == EAGAIN:
+        return None
+    _check(st, "orng_serve_try_submit")
     return t.value
 
 

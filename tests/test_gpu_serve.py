@@ -245,3 +245,112 @@ def test_serve_destroy_with_unreleased_results_still_drains(R):
     t0 = time.time()
     R.orng_serve_destroy(srv)  # must not wait for a release that never comes
     assert time.time() - t0 < 60
+
+
+def test_serve_try_submit_admits_at_once_or_returns_eagain(R, O):
+    """The non-blocking submit queues a request only when it can be admitted
+    at once; otherwise it returns EAGAIN and queues nothing."""
+    arena = _arena(1 << 20)
+    srv = R.orng_serve_create(arena.numel() * 4, arena=arena)
+    try:
+        big = dict(gen=0, dist=1, seed=5, ctr=6, offset=7, n=200_000)      # 800 KB
+        t1 = R.orng_serve_try_submit(srv, **big)
+        assert t1 is not None
+        # the arena holds t1's range until it is released
+        assert R.orng_serve_try_submit(srv, 3, 0, 1, 2, 3, 100_000) is None
+        res = R.orng_serve_wait(srv, t1)
+        assert np.array_equal(_read(arena, res), O.fill(0, 1, 5, 6, 7, 200_000).view(np.uint32))
+        # a blocking submit that does not fit waits in the queue; a small
+        # non-blocking one behind it is refused even though it would fit
+        t2 = R.orng_serve_submit(srv, 4, 2, 8, 9, 10, 150_000)              # 600 KB
+        time.sleep(0.05)
+        assert R.orng_serve_poll(srv, t2) is None
+        assert R.orng_serve_try_submit(srv, 0, 0, 1, 1, 0, 256) is None
+        st = R.orng_serve_stats(srv)
+        assert st["submitted"] == 2 and st["queued"] == 1
+        R.orng_serve_release(srv, t1)
+        res = R.orng_serve_wait(srv, t2)
+        assert np.array_equal(_read(arena, res), O.fill(4, 2, 8, 9, 10, 150_000).view(np.uint32))
+        t3 = R.orng_serve_try_submit(srv, 0, 0, 1, 1, 0, 256)
+        assert t3 is not None
+        res = R.orng_serve_wait(srv, t3)
+        assert np.array_equal(_read(arena, res), O.fill(0, 0, 1, 1, 0, 256).view(np.uint32))
+        R.orng_serve_release(srv, t2)
+        R.orng_serve_release(srv, t3)
+        with pytest.raises(R.OrngError) as e:
+            R.orng_serve_try_submit(srv, 0, 0, 1, 1, 0, 1 << 20)  # larger than the arena
+        assert e.value.status == R.ENOMEM
+    finally:
+        R.orng_serve_destroy(srv)
+
+
+def _failing_server(R, monkeypatch, step, **kw):
+    """A server whose step number `step` fails on the host before anything of
+    it is enqueued (the environment hook is read when the server is made)."""
+    monkeypatch.setenv("ORNG_SERVE_FAIL_STEP", str(step))
+    try:
+        return R.orng_serve_create(**kw)
+    finally:
+        monkeypatch.delenv("ORNG_SERVE_FAIL_STEP")
+
+
+def test_serve_first_step_failure_fails_every_ticket(R, monkeypatch):
+    print("serve: injected failure of step 1", flush=True)
+    arena = _arena(16 << 20)
+    srv = _failing_server(R, monkeypatch, 1, arena_bytes=arena.numel() * 4, arena=arena)
+    rng = np.random.default_rng(21)
+    qs = _random_reqs(rng, 12, 10, 14)
+    reqs = R.make_requests([q["gen"] for q in qs], [q["dist"] for q in qs],
+                           [q["seed"] for q in qs], [q["ctr"] for q in qs],
+                           [q["offset"] for q in qs], [q["n"] for q in qs], 0)
+    tickets = R.orng_serve_submit_many(srv, reqs)
+    for t in tickets:
+        with pytest.raises(R.OrngError) as e:
+            R.orng_serve_wait(srv, int(t), timeout_ns=30_000_000_000)
+        assert e.value.status == R.EHIP
+    with pytest.raises(R.OrngError) as e:
+        R.orng_serve_submit(srv, 0, 0, 1, 1, 0, 16)
+    assert e.value.status == R.EHIP
+    st = R.orng_serve_stats(srv)
+    assert st["failed"] == 12 and st["completed"] == 0
+    t0 = time.time()
+    with pytest.raises(R.OrngError) as e:
+        R.orng_serve_destroy(srv)
+    assert e.value.status == R.EHIP and time.time() - t0 < 30
+
+
+def test_serve_later_step_failure_keeps_finished_results(R, O, monkeypatch):
+    """Step 3 fails: the two steps queued before it are waited for, requests
+    they finished end done with the right words, every other ticket ends
+    EHIP, and nothing is left running."""
+    print("serve: injected failure of step 3", flush=True)
+    outs = torch.full((40, 1 << 14), -1, dtype=torch.int32, device="cuda")
+    srv = _failing_server(R, monkeypatch, 3, arena_bytes=1 << 20, step_words=1 << 15)
+    qs = [dict(gen=k % 9, dist=k % 3, seed=1000 + k, ctr=k, offset=3 * k, n=(1 << 14) - k)
+          for k in range(40)]
+    reqs = R.make_requests([q["gen"] for q in qs], [q["dist"] for q in qs],
+                           [q["seed"] for q in qs], [q["ctr"] for q in qs],
+                           [q["offset"] for q in qs], [q["n"] for q in qs],
+                           outs.data_ptr() + outs.stride(0) * 4 * np.arange(40))
+    tickets = R.orng_serve_submit_many(srv, reqs)
+    done, failed = [], []
+    for k, t in enumerate(tickets):
+        try:
+            res = R.orng_serve_wait(srv, int(t), timeout_ns=30_000_000_000)
+            assert res is not None, "ticket still running after the failure"
+            done.append(k)
+        except R.OrngError as e:
+            assert e.status == R.EHIP
+            failed.append(k)
+    assert failed, "the injected failure failed no request"
+    host = outs.cpu().numpy().view(np.uint32)
+    for k in done:
+        q = qs[k]
+        ref = O.fill(q["gen"], q["dist"], q["seed"], q["ctr"], q["offset"], q["n"])
+        assert np.array_equal(host[k, :q["n"]], ref.view(np.uint32)), ("request", k)
+    st = R.orng_serve_stats(srv)
+    assert st["failed"] == len(failed) and st["completed"] == len(done)
+    assert st["steps"] == 2
+    with pytest.raises(R.OrngError) as e:
+        R.orng_serve_destroy(srv)
+    assert e.value.status == R.EHIP
