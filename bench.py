@@ -256,6 +256,10 @@ def bench_batched(orng, inputs, stream, dev):
                                                     / (2 * half), 4)}}
 
 
+# the serving workload's HBM budget: 32 GB (10^9 bytes), in whole 256-byte granules
+SERVE_ARENA_BYTES = 32_000_000_000 // 256 * 256
+
+
 def _replay(orng, tr, idx, arena_bytes, open_loop):
     """Submit the requests of trace `tr` selected by `idx` to a fresh server
     (server-allocated outputs), at their arrival times (open loop) or all at
@@ -303,11 +307,12 @@ def _replay(orng, tr, idx, arena_bytes, open_loop):
 # VALU slots per particle-step of the paper's 2-D Brownian dynamics: one
 # Philox block (round 1 on the zero counter words folds to one xor3; 9 rounds
 # x (2 product-adds + 2 xor3): 37; the per-lane key schedule depends only on
-# the particle and is formed once per launch, not per step) and 26 float64
-# operations (two 53-bit conversions of 4 each; drag, kick and move, 9 per
-# component).  The published 78.6 TFLOP/s float64 vector rate is one
+# the particle and is formed once per launch, not per step) and 20 float64
+# operations (two 53-bit conversions of 4 each; per component the centred
+# kick (subtract, multiply), the decayed velocity (multiply, add) and the move
+# (multiply, add)).  The published 78.6 TFLOP/s float64 vector rate is one
 # operation per lane and clock, so each is one slot.
-BD2_SLOTS = 37 + 26
+BD2_SLOTS = 37 + 20
 BD2_BYTES_PER_STEP = 64  # one launch per step: load and store x, y, vx, vy
 
 
@@ -390,8 +395,8 @@ def bench_serve(orng, inputs, stream, dev, bulk_rates=None):
     m = tr["n"].size
     idx = np.arange(m)
     words = int(tr["n"].sum())
-    op = _replay(orng, tr, idx, 32 << 30, True)
-    sat = _replay(orng, tr, idx, 32 << 30, False)
+    op = _replay(orng, tr, idx, SERVE_ARENA_BYTES, True)
+    sat = _replay(orng, tr, idx, SERVE_ARENA_BYTES, False)
     # plain path on the same requests: one fill launch each, outputs in a ring
     cap = 8 << 30  # words
     buf = torch.empty(cap, dtype=torch.int32, device=dev)
@@ -416,6 +421,7 @@ def bench_serve(orng, inputs, stream, dev, bulk_rates=None):
         extra = {"bulk_rate_equiv_gsamples_s": round(words / t_bulk / 1e9, 2),
                  "saturated_vs_bulk_rate": round(gs(sat) / (words / t_bulk / 1e9), 4)}
     return {"requests": int(m), "samples": words, "offered_req_per_s": 5000,
+            "arena_bytes": SERVE_ARENA_BYTES,
             "open_loop": {"p50_ms": round(op["latency_p50_ms"], 4),
                           "p99_ms": round(op["latency_p99_ms"], 4),
                           "mean_ms": round(op["latency_mean_ms"], 4),
