@@ -119,7 +119,9 @@ def test_batched_errors(R):
 def test_batched_uneven_config_sampled(R, O):
     """10^5 Philox u32 streams, lengths log-uniform in [1, 2^20], random seeds,
     counters and offsets, outputs packed back to back: sampled positions of
-    sampled requests against the oracle, and batched == one launch per stream."""
+    sampled requests against the oracle one by one, then every word of every
+    request against the oracle's fills, and batched == one launch per
+    stream."""
     from paper_2310_19925_amd import inputs
     b = inputs.batched_requests()
     m = b["n"].size
@@ -145,14 +147,43 @@ def test_batched_uneven_config_sampled(R, O):
         ref = O.samples_at(0, 0, int(b["seed"][i]), np.full(sel.sum(), b["ctr"][i], np.uint32),
                            pos[sel])
         assert np.array_equal(got[sel], ref), ("request", i)
-    # plain path: same request list, one launch each, then compare samples
-    snap = buf[torch.tensor(idx, device="cuda")].clone()
+    # every word of every request against the oracle, in chunks of the
+    # packed output (requests that straddle a chunk are split)
+    _compare_packed(O, buf, b, 0, 0)
+    # plain path: same request list, one launch each, equal to the batch
+    snap = buf.clone()
     buf.fill_(-1)
     R.orng_fill_each(reqs)
     torch.cuda.synchronize()
-    assert torch.equal(buf[torch.tensor(idx, device="cuda")], snap)
-    del buf
+    assert torch.equal(buf, snap)
+    del buf, snap
     torch.cuda.empty_cache()
+
+
+def _compare_packed(O, buf, b, gen, dist, ch=1 << 26):
+    """Compare a packed batched output (request i at words out_off[i] ..
+    out_off[i + 1]) with the oracle's fills, chunk by chunk."""
+    starts = b["out_off"]
+    total = int(starts[-1])
+    host = torch.empty(ch, dtype=torch.int32, pin_memory=True)
+    i = 0
+    for c in range(0, total, ch):
+        e = min(total, c + ch)
+        host[: e - c].copy_(buf[c:e])
+        got = host.numpy().view(np.uint32)[: e - c]
+        ref = np.empty(e - c, np.uint32)
+        while i < starts.size - 1 and starts[i] < e:
+            a0, a1 = max(int(starts[i]), c), min(int(starts[i + 1]), e)
+            skip = a0 - int(starts[i])
+            ref[a0 - c:a1 - c] = O.fill(gen, dist, int(b["seed"][i]), int(b["ctr"][i]),
+                                        int(b["offset"][i]) + skip, a1 - a0).view(np.uint32)
+            if starts[i + 1] > e:
+                break  # continues into the next chunk
+            i += 1
+        if not np.array_equal(got, ref):
+            k = int(np.nonzero(got != ref)[0][0]) + c
+            r = int(np.searchsorted(starts, k, side="right") - 1)
+            pytest.fail("word %d of the packed output (request %d) differs" % (k, r))
 
 
 def test_autotune_writes_cache_and_keeps_results(R, O, tmp_path):

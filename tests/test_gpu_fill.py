@@ -2,9 +2,11 @@
 and distribution), through the C-ABI.
 
 Small cases are compared element by element: they span several spans/tiles
-and end in a ragged tail.  The 2^30-sample bulk configuration is compared on
-sampled positions (the oracle evaluates each one directly) and through
-properties that hold at any size.
+and end in a ragged tail.  A sweep with the grid capped at 1 and 7
+workgroups makes every kernel loop over many spans and is compared element
+by element.  The configured 2^30-sample bulk fills are compared element by
+element in chunks of 2^26 samples, and on sampled positions (the oracle
+evaluates each one directly) together with properties that hold at any size.
 """
 import numpy as np
 import pytest
@@ -198,3 +200,65 @@ def test_normal_pairs_errors(R):
         R.orng_normal_pairs(t, 0, 8, t, t)
     assert e.value.status == R.EINVAL
     R.orng_normal_pairs(0, 0, 0, 0, 0)
+
+
+@pytest.mark.parametrize("gen", range(5))
+def test_bulk_config_elementwise(R, O, gen):
+    """The configured bulk fills -- 2^30 samples of one stream (seed drawn from
+    PCG64, counter 0) as uint32, float32 uniform and float32 normal -- in the
+    launch configuration the benchmark times, compared with the oracle element
+    by element in chunks of 2^26 samples."""
+    from paper_2310_19925_amd import inputs
+    seed = inputs.bulk_seed()
+    n, ch = inputs.BULK_N, 1 << 26
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    host = torch.empty(ch, dtype=torch.int32, pin_memory=True)
+    try:
+        for dist in DISTS:
+            print("bulk elementwise gen=%d dist=%d" % (gen, dist), flush=True)
+            R.orng_fill(gen, dist, seed, 0, 0, n, out)
+            for c in range(0, n, ch):
+                host.copy_(out[c:c + ch])
+                got = host.numpy().view(np.uint32)
+                ref = bits(O.fill(gen, dist, seed, 0, c, ch))
+                if not np.array_equal(got, ref):
+                    bad = np.nonzero(got != ref)[0]
+                    pytest.fail("gen %d dist %d: %d mismatches, first at sample %d"
+                                % (gen, dist, bad.size, c + bad[0]))
+    finally:
+        del out
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("gen", GENS)
+def test_grid_stride_sweep(R, O, gen):
+    """The grid capped at 1 and at 7 workgroups, so that every wave of every
+    fill kernel loops over many spans (or Tyche tiles): each of the five
+    distributions from an odd offset into an output off the 16-byte grid, and
+    a multi-stream fill whose waves cross stream boundaries, element by
+    element against the oracle."""
+    seed = 0x9E3779B97F4A7C15
+    n = (1 << 20) + 2333
+    try:
+        for cap in (1, 7):
+            R.orng_set_launch(max_wgs=cap)
+            for dist in range(5):
+                k = 2 if dist >= 3 else 1
+                pad = 2 if k == 2 else 1
+                print("sweep gen=%d dist=%d cap=%d" % (gen, dist, cap), flush=True)
+                buf = torch.full((n * k + pad + 4,), -1, dtype=torch.int32, device="cuda")
+                out = buf[pad:pad + n * k]
+                R.orng_fill(gen, dist, seed, 5, 3, n, out)
+                torch.cuda.synchronize()
+                got = as_u32(buf)
+                ref = bits(O.fill(gen, dist, seed, 5, 3, n))
+                assert np.array_equal(got[pad:pad + n * k], ref), (gen, dist, cap)
+                assert np.all(got[:pad] == 0xFFFFFFFF) and np.all(got[pad + n * k:] == 0xFFFFFFFF)
+            per, ns = 20011, 37
+            m = torch.full((ns * per,), -1, dtype=torch.int32, device="cuda")
+            R.orng_fill_multi(gen, 2, seed, 9, ns, 11, per, m)
+            torch.cuda.synchronize()
+            ref = bits(O.fill_multi(gen, 2, seed, 9, ns, 11, per))
+            assert np.array_equal(as_u32(m), ref), (gen, "multi", cap)
+    finally:
+        R.orng_reset_launch()

@@ -354,3 +354,52 @@ def test_serve_later_step_failure_keeps_finished_results(R, O, monkeypatch):
     with pytest.raises(R.OrngError) as e:
         R.orng_serve_destroy(srv)
     assert e.value.status == R.EHIP
+
+
+def test_serve_saturated_trace_every_result(R, O):
+    """The whole serving workload (20,000 requests: sizes log-uniform in
+    [2^10, 2^26] words, every generator family and distribution) submitted at
+    once into a 32 GB arena, as in the saturated replay: every served output
+    equals orng_fill of the same request in full (compared on the device), and
+    its first, last and four random samples equal the oracle's."""
+    from paper_2310_19925_amd import inputs
+    tr = inputs.serve_trace()
+    m = tr["n"].size
+    arena = _arena(32_000_000_000 // 256 * 256)
+    srv = R.orng_serve_create(arena.numel() * 4, arena=arena)
+    ref = torch.empty(int(tr["n"].max()), dtype=torch.int32, device="cuda")
+    rng = np.random.default_rng(13)
+    gathered, wanted = [], []
+    print("serve: saturated trace of %d requests" % m, flush=True)
+    try:
+        reqs = R.make_requests(tr["gen"], tr["dist"], tr["seed"], tr["ctr"], tr["offset"],
+                               tr["n"], 0)
+        tickets = R.orng_serve_submit_many(srv, reqs)
+        for i, t in enumerate(tickets):
+            res = R.orng_serve_wait(srv, int(t))
+            n = int(tr["n"][i])
+            g, d = int(tr["gen"][i]), int(tr["dist"][i])
+            out = ref[:n]
+            R.orng_fill(g, d, int(tr["seed"][i]), int(tr["ctr"][i]), int(tr["offset"][i]), n, out)
+            off = (res["d_out"] - arena.data_ptr()) // 4
+            view = arena[off:off + n]
+            assert torch.equal(view, out), ("request", i)
+            js = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, 4)]))
+            gathered.append(view[torch.from_numpy(js).cuda()])
+            wanted.append((g, d, i, js))
+            R.orng_serve_release(srv, int(t))
+            if (i + 1) % 5000 == 0:
+                print("serve: %d results checked" % (i + 1), flush=True)
+        st = R.orng_serve_stats(srv)
+        assert st["completed"] == m and st["failed"] == 0
+    finally:
+        R.orng_serve_destroy(srv)
+    got = torch.cat(gathered).cpu().numpy().view(np.uint32)
+    del arena, ref
+    torch.cuda.empty_cache()
+    k = 0
+    for g, d, i, js in wanted:
+        exp = O.samples_at(g, d, int(tr["seed"][i]), np.full(js.size, tr["ctr"][i], np.uint32),
+                           (int(tr["offset"][i]) + js).astype(np.uint64))
+        assert np.array_equal(got[k:k + js.size], exp.view(np.uint32)), ("request", i)
+        k += js.size

@@ -67,8 +67,10 @@ def test_walk_errors(R):
 
 
 def test_walk_full_config(R, O):
-    """2^24 particles, 3-D, 10^4 steps, dt = 1e-3, D = 1, from the origin:
-    sampled particles bit-exact against the oracle, MSD against 6 t."""
+    """2^24 particles, 3-D, 10^4 steps, dt = 1e-3, D = 1, from the origin, in
+    one launch: a seeded subset of 65,536 particles spread over all ids (plus
+    the first and last) bit-exact against the oracle over all 10^4 steps, and
+    the MSD of all particles against 6 t."""
     from paper_2310_19925_amd import inputs
     cfg = inputs.WALK
     n, dim, steps = cfg["n_particles"], cfg["dim"], cfg["n_steps"]
@@ -78,10 +80,13 @@ def test_walk_full_config(R, O):
     R.orng_brownian(seed, 0, n, dim, 0, steps, cfg["dt"], cfg["D"], pos, msd, cfg["msd_every"])
     torch.cuda.synchronize()
     rng = np.random.default_rng(11)
-    ids = np.unique(np.concatenate([rng.integers(0, n, 256), [0, 1, n - 1]])).astype(np.uint32)
+    ids = np.unique(np.concatenate([rng.choice(n, 65536, replace=False), [0, 1, n - 1]]))
+    ids = ids.astype(np.uint32)
     got = pos[:, torch.from_numpy(ids.astype(np.int64)).cuda()].cpu().numpy()
+    print("walk: oracle on %d particles x %d steps" % (ids.size, steps), flush=True)
     ref, _ = O.brownian(seed, 0, ids=ids, dim=dim, n_steps=steps, dt=cfg["dt"], D=cfg["D"])
-    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    bad = np.nonzero((got.view(np.uint32) != ref.view(np.uint32)).any(axis=0))[0]
+    assert bad.size == 0, "%d particles differ, first id %d" % (bad.size, ids[bad[0]])
     m = msd.cpu().numpy() / n
     for q, val in enumerate(m):
         t = (q + 1) * cfg["msd_every"] * cfg["dt"]
@@ -91,3 +96,20 @@ def test_walk_full_config(R, O):
     # the last snapshot is the MSD of the final positions
     final = float((pos.double() ** 2).sum()) / n
     assert math.isclose(final, m[-1], rel_tol=1e-9)
+
+
+def test_walk_all_particles_100_steps(R, O):
+    """All 2^24 particles of the configured walk for 100 steps (a separate
+    launch in the benchmark's launch configuration), every position bit-exact
+    against the oracle."""
+    from paper_2310_19925_amd import inputs
+    cfg = inputs.WALK
+    n, dim, seed = cfg["n_particles"], cfg["dim"], inputs.bulk_seed()
+    print("walk all %d particles x 100 steps" % n, flush=True)
+    pos = torch.zeros((dim, n), dtype=torch.float32, device="cuda")
+    R.orng_brownian(seed, 0, n, dim, 0, 100, cfg["dt"], cfg["D"], pos)
+    torch.cuda.synchronize()
+    got = pos.cpu().numpy()
+    ref, _ = O.brownian(seed, 0, n_particles=n, dim=dim, n_steps=100, dt=cfg["dt"], D=cfg["D"])
+    bad = np.nonzero((got.view(np.uint32) != ref.view(np.uint32)).any(axis=0))[0]
+    assert bad.size == 0, "%d particles differ, first %d" % (bad.size, bad[0])
