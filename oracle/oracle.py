@@ -18,7 +18,7 @@ SRC = os.path.join(HERE, "orng_oracle.cc")
 LIB = os.path.join(HERE, "liborng_oracle.so")
 
 (PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE, THREEFRY4X32_13, THREEFRY2X64_13, TYCHE_I,
- SQUARES64) = range(9)
+ SQUARES64, PHILOX2X32) = range(10)
 U32, F32_UNIFORM, F32_NORMAL, F64_UNIFORM, F64_NORMAL = range(5)
 GENS = (PHILOX, THREEFRY4X32, THREEFRY2X64, SQUARES, TYCHE)
 DISTS = (U32, F32_UNIFORM, F32_NORMAL)  # the float32/u32 set; F64_UNIFORM is separate
@@ -52,6 +52,7 @@ def lib():
         P32, P64 = C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)
         sig = {
             "oracle_philox4x32_10": (None, [P32, P32, P32]),
+            "oracle_philox2x32_10": (None, [P32, u32, P32]),
             "oracle_threefry4x32_20": (None, [P32, P32, P32]),
             "oracle_threefry2x64_20": (None, [P64, P64, P64]),
             "oracle_threefry4x32_13": (None, [P32, P32, P32]),
@@ -113,6 +114,12 @@ def _arr32(vals):
 def philox4x32_10(ctr, key):
     out = (C.c_uint32 * 4)()
     lib().oracle_philox4x32_10(_arr32(ctr), _arr32(key), out)
+    return list(out)
+
+
+def philox2x32_10(ctr, key):
+    out = (C.c_uint32 * 2)()
+    lib().oracle_philox2x32_10(_arr32(ctr), int(key) & 0xFFFFFFFF, out)
     return list(out)
 
 

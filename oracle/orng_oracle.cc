@@ -54,6 +54,19 @@ void philox_round(uint32_t x[4], const uint32_t k[2]) {
 }
 
 /* ---------------------------------------------------------------------------
+ * Philox2x32-10 (same source): the two-word member of the Philox family.  One
+ * round multiplies the first word by one odd constant; the new first word is
+ * the product's high half XOR the second word XOR the 32-bit round key, the
+ * new second word is its low half.  The key is bumped by the first Weyl
+ * constant between rounds.  Its key is a single 32-bit word, so this library
+ * offers it for seeds below 2^32 (the paper's Squares is likewise limited to
+ * 32-bit seeds, section 3.1).  Parity unpinned (no implementation of it is at
+ * hand); pinned by round inversion, distinct outputs over enumerated
+ * counters and statistics.
+ * ------------------------------------------------------------------------- */
+const uint32_t PHILOX2_M = 0xD256D193u;
+
+/* ---------------------------------------------------------------------------
  * Threefry4x32-20 (Salmon et al., SC'11, section 3.2; Threefish-style ARX).
  * Key schedule: four key words plus their XOR with the Skein parity constant.
  * The key is injected before round 0 and after every fourth round, with the
@@ -118,11 +131,19 @@ const uint64_t TYCHE_TILE = 16384, TYCHE_LANES = 64, TYCHE_BLOCKS = 64;
  *   Threefry2x64-20 : counter (p/4, ctr) as 64-bit words, key (seed, 0);
  *                     the four 32-bit words are lo X0, hi X0, lo X1, hi X1
  *   the 13-round Threefry variants: as their 20-round forms
+ *   Philox2x32-10   : word p is word p mod 2 of Philox2x32(counter (p/2, ctr),
+ *                     key lo seed); the block of four words p/4 holds the
+ *                     two-word blocks 2(p/4) and 2(p/4) + 1
  * word(p) is word p mod 4 of that block.
  * ------------------------------------------------------------------------- */
 void counter_block(int gen, uint64_t seed, uint32_t ctr, uint64_t b, uint32_t out[4]) {
     uint32_t lo = (uint32_t)seed, hi = (uint32_t)(seed >> 32);
-    if (gen == OR_PHILOX) {
+    if (gen == OR_PHILOX2X32) {
+        for (uint64_t h = 0; h < 2; ++h) {
+            const uint32_t c[2] = {(uint32_t)(2 * b + h), ctr};
+            oracle_philox2x32_10(c, lo, out + 2 * h);
+        }
+    } else if (gen == OR_PHILOX) {
         uint32_t c[4] = {(uint32_t)b, ctr, 0u, 0u};
         uint32_t k[2] = {lo, hi};
         oracle_philox4x32_10(c, k, out);
@@ -241,7 +262,9 @@ void samples_range(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t p0, 
     }
 }
 
-bool valid_gen(int g) { return g >= OR_PHILOX && g <= OR_SQUARES64; }
+bool valid_gen(int g) { return g >= OR_PHILOX && g <= OR_PHILOX2X32; }
+/* Philox2x32-10 has a 32-bit key: its seeds must be below 2^32 */
+bool valid_seed(int g, uint64_t seed) { return g != OR_PHILOX2X32 || seed <= 0xFFFFFFFFull; }
 bool valid_dist(int d) { return d >= OR_U32 && d <= OR_F64_NORMAL; }
 /* bytes per sample, and stream positions (words) per sample */
 bool is_f64(int dist) { return dist == OR_F64_UNIFORM || dist == OR_F64_NORMAL; }
@@ -278,6 +301,19 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
         philox_round(x, k);
     }
     std::memcpy(out, x, sizeof x);
+}
+
+void oracle_philox2x32_10(const uint32_t ctr[2], uint32_t key, uint32_t out[2]) {
+    uint32_t a = ctr[0], b = ctr[1], k = key;
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) k += PHILOX_W0;
+        const uint64_t prod = (uint64_t)PHILOX2_M * a;
+        const uint32_t hi = (uint32_t)(prod >> 32), lo = (uint32_t)prod;
+        a = hi ^ b ^ k;
+        b = lo;
+    }
+    out[0] = a;
+    out[1] = b;
 }
 
 /* R rounds of Threefry4x32: the key is injected before round 0 and after
@@ -613,7 +649,7 @@ void oracle_normal_pair_n(const uint32_t *x0, const uint32_t *x1, uint64_t n, fl
 
 int oracle_fill(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t offset, uint64_t n,
                 void *out, int nthreads) {
-    if (!valid_gen(gen) || !valid_dist(dist)) return -1;
+    if (!valid_gen(gen) || !valid_dist(dist) || !valid_seed(gen, seed)) return -1;
     const uint64_t lim = sample_limit(dist), sb = sample_bytes(dist);
     if (offset > lim || n > lim - offset) return -2;
     char *o = (char *)out;
@@ -628,7 +664,7 @@ int oracle_fill(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t offset,
 
 int oracle_fill_multi(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t n_streams,
                       uint64_t offset, uint64_t per_stream, void *out, int nthreads) {
-    if (!valid_gen(gen) || !valid_dist(dist)) return -1;
+    if (!valid_gen(gen) || !valid_dist(dist) || !valid_seed(gen, seed)) return -1;
     const uint64_t lim = sample_limit(dist), sb = sample_bytes(dist);
     if (offset > lim || per_stream > lim - offset) return -2;
     if (n_streams && (uint64_t)ctr0 + n_streams - 1 > 0xFFFFFFFFull) return -2;
@@ -889,6 +925,7 @@ int oracle_particle_streams(int gen, uint64_t seed0, uint32_t n_particles, uint3
     if (!valid_gen(gen) || draws < 1 || draws > 16) return -1;
     if (n_iters && (uint64_t)ctr0 + n_iters - 1 > 0xFFFFFFFFull) return -2;
     if (n_particles && seed0 + (n_particles - 1) < seed0) return -2;
+    if (n_particles && !valid_seed(gen, seed0 + (n_particles - 1))) return -2;
     const uint64_t units = (uint64_t)n_iters * n_particles;
     parallel_ranges(units, nthreads, [&](uint64_t a, uint64_t b, int) {
         for (uint64_t u = a; u < b; ++u) {
@@ -928,7 +965,7 @@ int32_t oracle_range_i32(uint32_t w0, uint32_t w1, int32_t lo, int32_t hi) {
 int oracle_fill_range(int gen, uint64_t seed, uint32_t ctr0, uint32_t n_streams,
                       uint64_t offset, uint64_t per_stream, int32_t lo, int32_t hi,
                       int32_t *out, int nthreads) {
-    if (!valid_gen(gen) || lo >= hi) return -1;
+    if (!valid_gen(gen) || lo >= hi || !valid_seed(gen, seed)) return -1;
     const uint64_t lim = 1ull << 31;
     if (offset > lim || per_stream > lim - offset) return -2;
     if (n_streams && (uint64_t)ctr0 + n_streams - 1 > 0xFFFFFFFFull) return -2;

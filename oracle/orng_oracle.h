@@ -41,11 +41,13 @@ extern "C" {
 /* generator and distribution codes (same numbering as the public API; the
    numbers are part of the interface, not shared code) */
 enum { OR_PHILOX = 0, OR_THREEFRY4X32 = 1, OR_THREEFRY2X64 = 2, OR_SQUARES = 3, OR_TYCHE = 4,
-       OR_THREEFRY4X32_13 = 5, OR_THREEFRY2X64_13 = 6, OR_TYCHE_I = 7, OR_SQUARES64 = 8 };
+       OR_THREEFRY4X32_13 = 5, OR_THREEFRY2X64_13 = 6, OR_TYCHE_I = 7, OR_SQUARES64 = 8,
+       OR_PHILOX2X32 = 9 };
 enum { OR_U32 = 0, OR_F32_UNIFORM = 1, OR_F32_NORMAL = 2, OR_F64_UNIFORM = 3, OR_F64_NORMAL = 4 };
 
 /* --- raw generator cores ------------------------------------------------ */
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void oracle_philox2x32_10(const uint32_t ctr[2], uint32_t key, uint32_t out[2]);
 void oracle_threefry4x32_20(const uint32_t ctr[4], const uint32_t key[4], uint32_t out[4]);
 void oracle_threefry2x64_20(const uint64_t ctr[2], const uint64_t key[2], uint64_t out[2]);
 void oracle_threefry4x32_13(const uint32_t ctr[4], const uint32_t key[4], uint32_t out[4]);
@@ -61,7 +63,9 @@ uint32_t oracle_tyche_i_next(uint32_t st[4]);      /* one inverse MIX, returns b
 uint64_t oracle_squares64(uint64_t ctr, uint64_t key);  /* five rounds, 64-bit output */
 
 /* --- stream model -------------------------------------------------------- */
-/* word at position p of stream (seed, ctr) of generator gen */
+/* word at position p of stream (seed, ctr) of generator gen (Philox2x32-10
+   keys with the low 32 bits of seed; the entry points below reject its seeds
+   of 2^32 and above) */
 uint32_t oracle_word(int gen, uint64_t seed, uint32_t ctr, uint64_t p);
 /* sample at position p of the given distribution; writes 4 bytes to *out
    (8 for OR_F64_UNIFORM and OR_F64_NORMAL, whose sample p is made from words

@@ -132,7 +132,7 @@ def test_variant_streams_statistics(O, gen):
 
 
 def test_variants_through_every_oracle_entry_point(O):
-    for gen in (7, 8):
+    for gen in (7, 8, 9):
         f = O.fill(gen, O.F32_UNIFORM, 1, 2, 3, 1000)
         at = O.samples_at(gen, O.F32_UNIFORM, 1, np.full(3, 2, np.uint32),
                           np.array([3, 500, 1002], np.uint64))
@@ -142,4 +142,4 @@ def test_variants_through_every_oracle_entry_point(O):
         ps = O.particle_streams(gen, 10, 4, 3, 6, 2).reshape(2, 4, 3)
         assert np.array_equal(ps[1, 2], O.fill(gen, O.U32, 12, 7, 0, 3))
     with pytest.raises(ValueError):
-        O.fill(9, O.U32, 1, 2, 3, 10)
+        O.fill(10, O.U32, 1, 2, 3, 10)
