@@ -54,9 +54,15 @@ VALU_PEAK_TSLOTS = 256 * 64 * 2.4e9 / 1e12
 #   Threefry4x32-13: 11 full rounds x 6 + rounds 1-2 (7) + counter add 1 + 3
 #     injections x 2 (no injection after round 13): 80 / 4 words
 #   Threefry2x64-13: 12 rounds x 5 + round 1 (3) + counter add 1 + 3 x 2: 70 / 4 words
+#   Philox2x32-10: 10 rounds x (1 product + 1 xor3) per two-word block: 10 / word
 SLOTS_GEN = {0: 38 / 4, 1: 128 / 4, 2: 109 / 4, 3: 13 + 3 / 4, 4: 12 + 20 * 12 / 256,
-             5: 80 / 4, 6: 70 / 4, 7: 12 + 20 * 12 / 256, 8: (5 * 3 + 2 + 1) / 2 + 3 / 4}
+             5: 80 / 4, 6: 70 / 4, 7: 12 + 20 * 12 / 256, 8: (5 * 3 + 2 + 1) / 2 + 3 / 4,
+             9: 10.0}
 SLOTS_DIST = {0: 0.0, 1: 2.0, 2: 36.5 / 2}
+# Fused walk, per particle, step and coordinate: one Philox word (9.5 slots),
+# one Box-Muller sample (half a pair, 18.25) and the fmaf update (an fp32
+# operation, 0.5): 28.25 slots; 84.75 per particle-step in 3-D.
+WALK_SLOTS_PER_DIM = 38 / 4 + 36.5 / 2 + 0.5
 # float64 uniform: two words per sample, then shift, two conversions, one
 # exact fma and one scaling (float64 operations: one slot each at the
 # published 78.6 TFLOP/s vector rate); 8 bytes written per sample
@@ -133,44 +139,66 @@ def traffic_bytes(gen, dist):
     return round(f * 1024 * TRAFFIC_FACTORS[0] + w * 1024 * TRAFFIC_FACTORS[1])
 
 
+def key32(gen, seed):
+    """Philox2x32-10 (generator 9) keys with one 32-bit word: its fills take
+    the low word of the seed the other generators use."""
+    return seed & 0xFFFFFFFF if gen == 9 else seed
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
 def cpu_threads():
+    """Every host core this process may run on."""
     try:
-        n = len(os.sched_getaffinity(0))
+        return max(1, len(os.sched_getaffinity(0)))
     except AttributeError:
-        n = os.cpu_count() or 1
-    return max(1, min(n, 16))
+        return max(1, os.cpu_count() or 1)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(seed, target_s=30.0):
-    """Oracle (test infrastructure, untuned) on the host cores: the same 15
-    fills on a bounded sample of each, scaled to GSamples/s.  The sample is
-    sized from a 2^20-sample trial run; the trial's fixed costs make the
-    estimate about twice the real time, so target_s = 30 gives ~10-15 s."""
+    """Oracle (test infrastructure, untuned) built for this host with -O3
+    -march=native -ffp-contract=off, on every host core: the same 15 fills on
+    a bounded sample of each, scaled to GSamples/s.  The sample is sized from
+    a 2^20-sample trial run; the trial's fixed costs make the estimate about
+    twice the real time, so target_s = 30 gives ~10-15 s."""
     import numpy as np
     from oracle import oracle as O
+    L = O.lib_native()
     th = cpu_threads()
     per = 1 << 20
+    buf_u = np.empty(per, np.uint32)
     t0 = time.perf_counter()
     for g in range(5):
         for d in range(3):
-            O.fill(g, d, seed, 0, 0, per, nthreads=th)
+            assert L.oracle_fill(g, d, seed, 0, 0, per, buf_u.ctypes.data, th) == 0
     t_small = time.perf_counter() - t0
+    # the native build computes the same words as the test-suite's build
+    ref = O.fill(4, 2, seed, 0, 0, per)
+    assert np.array_equal(buf_u, ref.view(np.uint32))
     scale = max(1, min(1024, int(target_s / max(t_small, 1e-3))))  # at most the whole 2^30
     per = per * scale
     buf_u = np.empty(per, np.uint32)
     t0 = time.perf_counter()
     for g in range(5):
         for d in range(3):
-            out = buf_u if d == 0 else buf_u.view(np.float32)
-            rc = O.lib().oracle_fill(g, d, seed, 0, 0, per, out.ctypes.data, th)
-            assert rc == 0
+            assert L.oracle_fill(g, d, seed, 0, 0, per, buf_u.ctypes.data, th) == 0
     dt = time.perf_counter() - t0
     return {"value": round(15 * per / dt / 1e9, 4), "unit": "GSamples/s", "cores": th,
-            "kind": "oracle",
+            "kind": "oracle", "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "build": "g++ " + " ".join(O.NATIVE_FLAGS) + " -ffp-contract=off",
             "sample": "first %d samples of each of the 15 fills (gen x dist), %.1f s wall"
                       % (per, dt)}
 
@@ -213,8 +241,9 @@ def bench_plain_multi(orng, inputs, stream, dev):
 
 def bench_batched(orng, inputs, stream, dev):
     """10^5 Philox u32 streams of log-uniform length in [1, 2^20] words, packed
-    back to back: batched (one persistent launch) vs one launch per stream vs
-    one plain fill of the same number of words."""
+    back to back: batched (the tuned schedule, with the persistent work-queue
+    kernel and the allocation-free call timed beside it) vs one launch per
+    stream vs one plain fill of the same number of words."""
     import torch
     b = inputs.batched_requests()
     total = int(b["out_off"][-1])
@@ -222,6 +251,18 @@ def bench_batched(orng, inputs, stream, dev):
     reqs = orng.make_requests(0, 0, b["seed"], b["ctr"], b["offset"], b["n"],
                               buf.data_ptr() + 4 * b["out_off"][:-1])
     t_batched = _time_events(stream, lambda: orng.orng_fill_batched(reqs, stream), 5)
+    # The persistent work-queue kernel on the same batch: a grid cap selects it
+    # (4 workgroups per compute unit, the tuner's persistent shape); the tuned
+    # default for Philox u32 is the static one-workgroup-per-tile schedule.
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    orng.orng_set_launch(max_wgs=4 * cus)
+    try:
+        t_queue = _time_events(stream, lambda: orng.orng_fill_batched(reqs, stream), 5)
+    finally:
+        orng.orng_reset_launch()
+    # the allocation-free call (tables in the library's fixed device array;
+    # its row upload is part of the timed span)
+    t_noalloc = _time_events(stream, lambda: orng.orng_fill_batched_noalloc(reqs, stream), 5)
     t_each = _time_events(stream, lambda: orng.orng_fill_each(reqs, stream), 2)
     half = total // 2
     t_plain = _time_events(stream, lambda: orng.orng_fill_multi(0, 0, 42, 0, 2, 0, half, buf,
@@ -244,6 +285,10 @@ def bench_batched(orng, inputs, stream, dev):
     g = lambda ms, words: round(words / (ms * 1e-3) / 1e9, 2)
     return {"requests": int(b["n"].size), "words": total,
             "batched_ms": round(t_batched, 3), "batched_gsamples_s": g(t_batched, total),
+            "schedule": "static (one workgroup per tile)",
+            "queue_ms": round(t_queue, 3), "queue_gsamples_s": g(t_queue, total),
+            "queue_vs_plain": round(t_plain / t_queue * total / (2 * half), 4),
+            "noalloc_ms": round(t_noalloc, 3), "noalloc_gsamples_s": g(t_noalloc, total),
             "each_ms": round(t_each, 3), "each_gsamples_s": g(t_each, total),
             "plain_ms": round(t_plain, 3), "plain_gsamples_s": g(t_plain, 2 * half),
             "batched_vs_plain": round(t_plain / t_batched * total / (2 * half), 4),
@@ -356,9 +401,10 @@ def bench_bd2(orng, inputs, stream, dev, per_step_too=True):
 # one counter block for Philox/Threefry (3 of its 4 words used); three
 # Squares words plus the y product; Tyche seeds an instance (20 MIX) and runs
 # 4 more (12 slots per MIX); the 13-round Threefry blocks; Tyche-i as Tyche;
-# Squares64 two calls (5 rounds of 3 slots, the 64-bit adds and the XOR).
+# Squares64 two calls (5 rounds of 3 slots, the 64-bit adds and the XOR);
+# Philox2x32 two two-word blocks.
 PART_SLOTS_3 = {0: 38, 1: 128, 2: 109, 3: 3 + 3 * 13, 4: 24 * 12, 5: 80, 6: 70, 7: 24 * 12,
-                8: 3 + 2 * 18}
+                8: 3 + 2 * 18, 9: 40}
 
 
 def bench_particles(orng, inputs, stream, dev):
@@ -369,7 +415,7 @@ def bench_particles(orng, inputs, stream, dev):
     T = (1 << 30) // (P * D)
     out = torch.empty(T * P * D, dtype=torch.int32, device=dev)
     res = []
-    for g in range(9):
+    for g in range(10):
         ms = _time_events(stream, lambda: orng.orng_particle_streams(g, 1, P, D, 1, T, out,
                                                                      stream), 3)
         words = T * P * D
@@ -527,11 +573,12 @@ def main():
     # and the 13-round Threefry variants (4 GiB each)
     extra = []
     if not args.only:
-        cases = [(g, 3) for g in range(9)] + [(g, 4) for g in range(9)] + \
-            [(g, d) for g in (5, 6, 7, 8) for d in range(3)]
+        cases = [(g, 3) for g in range(10)] + [(g, 4) for g in range(10)] + \
+            [(g, d) for g in (5, 6, 7, 8, 9) for d in range(3)]
         for g, d in cases:
             ns = n // 2 if d in (3, 4) else n
-            ms = _time_events(stream, lambda: orng.orng_fill(g, d, seed, 0, 0, ns, out, stream), 3)
+            sg = key32(g, seed)
+            ms = _time_events(stream, lambda: orng.orng_fill(g, d, sg, 0, 0, ns, out, stream), 3)
             rf = roofs(g, d, ns, ms)
             gbs = 4.0 * n / (ms * 1e-3) / 1e9
             extra.append({"gen": inputs.GEN_NAMES[g], "dist": inputs.DIST_NAMES[d],
@@ -540,9 +587,10 @@ def main():
                           "valu_frac": rf["valu_frac"], "binding": rf["binding"],
                           "binding_frac": rf["binding_frac"]})
         # integers in [lo, hi), 2^30 int32 samples each
-        for g in range(9):
+        for g in range(10):
+            sg = key32(g, seed)
             ms = _time_events(stream, lambda: orng.orng_fill_range(
-                g, seed, 0, 1, 0, n, RANGE_LO, RANGE_HI, out, stream), 3)
+                g, sg, 0, 1, 0, n, RANGE_LO, RANGE_HI, out, stream), 3)
             rf = roofs(g, "range", n, ms)
             gbs = 4.0 * n / (ms * 1e-3) / 1e9
             extra.append({"gen": inputs.GEN_NAMES[g], "dist": "i32_range",
@@ -604,7 +652,11 @@ def main():
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         m = (msd.cpu().numpy() / w["n_particles"]).tolist()
+        ps = w["n_steps"] * w["n_particles"]
+        wslots = WALK_SLOTS_PER_DIM * w["dim"] * ps
         result["walk"] = {"steps_per_s": round(w["n_steps"] / (ms * 1e-3), 1),
+                          "valu_tslots_s": round(wslots / (ms * 1e-3) / 1e12, 2),
+                          "valu_frac": round(wslots / (ms * 1e-3) / 1e12 / VALU_PEAK_TSLOTS, 4),
                           "particle_steps_per_s": round(w["n_steps"] * w["n_particles"]
                                                         / (ms * 1e-3), 1),
                           "ms": round(ms, 3), "n_particles": w["n_particles"], "dim": w["dim"],

@@ -13,7 +13,8 @@
  *
  * Generators (section 3.1): Philox4x32-10 and Threefry (4x32-20, 2x64-20)
  * after Salmon et al. SC'11, Squares (32-bit output, four rounds) after
- * Widynski 2020, Tyche after Neves and Araujo 2012.
+ * Widynski 2020, Tyche after Neves and Araujo 2012; and the variants
+ * Threefry 13-round, Tyche-i, Squares64 and Philox2x32-10.
  *
  * Conventions shared by every call:
  *  - Device pointers are caller-owned HIP device allocations; the library never
@@ -46,7 +47,8 @@ enum {
     ORNG_THREEFRY4X32_13 = 5, /* the Threefry rounds stopped after round 13 */
     ORNG_THREEFRY2X64_13 = 6,
     ORNG_TYCHE_I = 7,         /* Tyche on the inverse of its mixing round */
-    ORNG_SQUARES64 = 8        /* five-round Squares, 64 bits (two words) per call */
+    ORNG_SQUARES64 = 8,       /* five-round Squares, 64 bits (two words) per call */
+    ORNG_PHILOX2X32 = 9       /* two-word Philox; one 32-bit key word: seeds < 2^32 */
 };
 
 /* distributions; samples are 4 bytes, 8 for the two float64 ones */
@@ -102,11 +104,16 @@ enum {
  *                    Tyche's MIX (its four steps undone in reverse order)
  *   Squares64      : word p = low (p even) or high half of
  *                    squares64(counter (ctr << 32) | p/2, key K(seed))
+ *   Philox2x32-10  : word p = word p%2 of Philox2x32(counter (p/2, ctr),
+ *                    key seed); its key is one 32-bit word, so it takes
+ *                    seeds below 2^32 only (as the paper's Squares takes
+ *                    32-bit seeds, section 3.1)
  * Arguments: gen, dist (enums above); d_out: device buffer of n samples
  * (n * 4 bytes, 4-byte aligned; n * 8 bytes, 8-byte aligned for the float64
  * distributions).
- * Errors: EINVAL (enum, NULL, alignment), ERANGE (offset + n past the last
- *         sample: 2^32, or 2^31 for the float64 distributions).
+ * Errors: EINVAL (enum, NULL, alignment, a Philox2x32 seed of 2^32 or more),
+ *         ERANGE (offset + n past the last sample: 2^32, or 2^31 for the
+ *         float64 distributions).
  */
 int orng_fill(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t offset, uint64_t n,
               void *d_out, void *stream);
@@ -133,7 +140,8 @@ int orng_fill_multi(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t n_
  * d_out: device buffer of n_iters * n_particles * draws 32-bit words.
  * Errors: EINVAL (gen, draws not in 1..16, NULL or misaligned d_out), ERANGE
  *         (ctr0 + n_iters - 1 > 2^32 - 1, seed0 + n_particles - 1 overflows
- *         64 bits).  n_particles = 0 or n_iters = 0 does nothing.
+ *         64 bits, or for Philox2x32 exceeds 2^32 - 1).  n_particles = 0 or
+ *         n_iters = 0 does nothing.
  */
 int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particles, uint32_t draws,
                           uint32_t ctr0, uint32_t n_iters, void *d_out, void *stream);
@@ -151,7 +159,8 @@ int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particles, uint32_
  * Positions: offset + per_stream <= 2^31 samples per stream.
  * d_out: device buffer of n_streams * per_stream int32 (caller-owned, 4-byte
  *   aligned; 16-byte alignment of d_out + offset is the fast path).
- * Errors: EINVAL (gen, lo >= hi, NULL or misaligned d_out with work to do),
+ * Errors: EINVAL (gen, lo >= hi, a Philox2x32 seed of 2^32 or more, NULL or
+ *         misaligned d_out with work to do),
  *         ERANGE (offset + per_stream > 2^31, ctr0 + n_streams - 1 > 2^32 - 1).
  *         n_streams = 0 or per_stream = 0 does nothing.
  */

@@ -43,11 +43,9 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        build(force=False)  # rebuilds when the sources are newer than the library
-        L = C.CDLL(LIB)
+def _bind(L):
+    """Declare the C signatures of the oracle library L."""
+    if True:
         u32, u64, i32, vp, f32 = C.c_uint32, C.c_uint64, C.c_int, C.c_void_p, C.c_float
         P32, P64 = C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)
         sig = {
@@ -99,8 +97,37 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
-        _lib = L
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)  # rebuilds when the sources are newer than the library
+        _lib = _bind(C.CDLL(LIB))
     return _lib
+
+
+NATIVE_FLAGS = ["-O3", "-march=native"]
+_native = None
+
+
+def lib_native():
+    """The same oracle source built for the host it runs on (-O3
+    -march=native, contraction still off, no fast-math), into a temporary
+    directory, for timing the oracle as a CPU baseline.  Every result is the
+    same as lib()'s: each float expression stays one IEEE operation."""
+    global _native
+    if _native is None:
+        import tempfile
+        d = tempfile.mkdtemp(prefix="orng_oracle_native_")
+        path = os.path.join(d, "liborng_oracle_native.so")
+        flags = [f for f in CXXFLAGS if not f.startswith("-O")] + NATIVE_FLAGS
+        subprocess.run(["g++", *flags, SRC, "-o", path], check=True)
+        _native = _bind(C.CDLL(path))
+    return _native
+
+
 
 
 def default_threads() -> int:

@@ -38,7 +38,7 @@ static int hip_status(hipError_t e) {
     return ORNG_EHIP;
 }
 
-static bool valid_gen(int g) { return g >= ORNG_PHILOX4X32_10 && g <= ORNG_SQUARES64; }
+static bool valid_gen(int g) { return g >= ORNG_PHILOX4X32_10 && g <= ORNG_PHILOX2X32; }
 static bool valid_dist(int d) { return d >= ORNG_U32 && d <= ORNG_F64_NORMAL; }
 
 }  // namespace orng
@@ -49,7 +49,7 @@ extern "C" {
 
 int orng_fill(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t offset, uint64_t n,
               void *d_out, void *stream) {
-    if (!valid_gen(gen) || !valid_dist(dist)) return ORNG_EINVAL;
+    if (!valid_gen(gen) || !valid_dist(dist) || !seed_ok(gen, seed)) return ORNG_EINVAL;
     const uint64_t k = words_per_sample(dist), lim = sample_limit(dist);
     if (offset > lim || n > lim - offset) return ORNG_ERANGE;
     if (n == 0) return ORNG_OK;
@@ -60,7 +60,7 @@ int orng_fill(int gen, int dist, uint64_t seed, uint32_t ctr, uint64_t offset, u
 
 int orng_fill_multi(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t n_streams,
                     uint64_t offset, uint64_t per_stream, void *d_out, void *stream) {
-    if (!valid_gen(gen) || !valid_dist(dist)) return ORNG_EINVAL;
+    if (!valid_gen(gen) || !valid_dist(dist) || !seed_ok(gen, seed)) return ORNG_EINVAL;
     const uint64_t k = words_per_sample(dist), lim = sample_limit(dist);
     if (offset > lim || per_stream > lim - offset) return ORNG_ERANGE;
     if (n_streams && (uint64_t)ctr0 + n_streams - 1 > 0xFFFFFFFFull) return ORNG_ERANGE;

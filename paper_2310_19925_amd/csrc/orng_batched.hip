@@ -232,7 +232,8 @@ static void *batched_kernel(const BatchShape &s, bool f64n) {
 }
 
 int validate_request(const orng_req_t &r) {
-    if (r.gen > ORNG_SQUARES64 || r.dist > ORNG_F64_NORMAL || r.flags != 0) return ORNG_EINVAL;
+    if (r.gen > ORNG_PHILOX2X32 || r.dist > ORNG_F64_NORMAL || r.flags != 0) return ORNG_EINVAL;
+    if (!seed_ok((int)r.gen, r.seed)) return ORNG_EINVAL;
     const uint64_t k = words_per_sample((int)r.dist), lim = sample_limit((int)r.dist);
     if (r.offset > lim || r.n > lim - r.offset) return ORNG_ERANGE;
     if (r.n == 0) return ORNG_OK;

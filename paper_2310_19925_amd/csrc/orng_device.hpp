@@ -23,9 +23,10 @@
 namespace orng {
 
 enum GenId : int { G_PHILOX = 0, G_TF4X32 = 1, G_TF2X64 = 2, G_SQUARES = 3, G_TYCHE = 4,
-                   G_TF4X32_13 = 5, G_TF2X64_13 = 6, G_TYCHE_I = 7, G_SQUARES64 = 8 };
+                   G_TF4X32_13 = 5, G_TF2X64_13 = 6, G_TYCHE_I = 7, G_SQUARES64 = 8,
+                   G_PHILOX2X32 = 9 };
 enum DistId : int { D_U32 = 0, D_UNIFORM = 1, D_NORMAL = 2, D_F64U = 3, D_F64N = 4 };
-constexpr int NGEN = 9, NDIST = 5;
+constexpr int NGEN = 10, NDIST = 5;
 
 // Tyche and Tyche-i share the tile layout (no random access within a
 // substream); every other generator is counter-based with 4-word blocks.
@@ -66,6 +67,30 @@ __device__ __forceinline__ void philox_block(uint32_t c0, uint32_t c1, const Key
         x2 = n2;
     }
     o[0] = x0; o[1] = x1; o[2] = x2; o[3] = x3;
+}
+
+// ---------------------------------------------------------------------------
+// Philox2x32-10 (the two-word Philox).  Its key is one 32-bit word, the low
+// word of a seed below 2^32, so its round keys are the first column of the
+// Philox4x32 schedule.  Positions 4 blk .. 4 blk + 3 are the two-word blocks
+// (2 blk, c1) and (2 blk + 1, c1), computed side by side: one 32x32->64
+// product and one xor3 per round and block.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox2_block(uint32_t blk, uint32_t c1, const KeySched &ks,
+                                              uint32_t o[4]) {
+    uint32_t a0 = 2u * blk, a1 = 2u * blk + 1u, b0 = c1, b1 = c1;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)a0 * 0xD256D193u;
+        const uint64_t p1 = (uint64_t)a1 * 0xD256D193u;
+        const uint32_t n0 = xor3((uint32_t)(p0 >> 32), b0, ks.k[r][0]);
+        const uint32_t n1 = xor3((uint32_t)(p1 >> 32), b1, ks.k[r][0]);
+        b0 = (uint32_t)p0;
+        b1 = (uint32_t)p1;
+        a0 = n0;
+        a1 = n1;
+    }
+    o[0] = a0; o[1] = b0; o[2] = a1; o[3] = b1;
 }
 
 // Block 0 of Philox stream (seed, c1) with the key in VGPRs, for kernels in
@@ -603,6 +628,8 @@ __device__ __forceinline__ void counter_block(uint32_t blk, uint32_t ctr, const 
         tf2_block<13>(blk, ctr, ks, w);
     } else if constexpr (G == G_SQUARES64) {
         squares64_block(blk, ctr, ks.sqkey, w);
+    } else if constexpr (G == G_PHILOX2X32) {
+        philox2_block(blk, ctr, ks, w);
     } else {  // G_SQUARES
         squares_block(blk, ctr, ks.sqkey, w);
     }

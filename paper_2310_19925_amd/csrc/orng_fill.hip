@@ -125,6 +125,7 @@ static void *pick_kernel(int gen, int dist, bool units, bool nt) {
     case G_TF2X64_13: return pick_d<G_TF2X64_13>(dist, units, nt);
     case G_TYCHE_I: return pick_d<G_TYCHE_I>(dist, units, nt);
     case G_SQUARES64: return pick_d<G_SQUARES64>(dist, units, nt);
+    case G_PHILOX2X32: return pick_d<G_PHILOX2X32>(dist, units, nt);
     default: return pick_d<G_TYCHE>(dist, units, nt);
     }
 }

@@ -20,6 +20,9 @@ constexpr uint64_t PERIOD = 1ull << 32;
 inline uint64_t words_per_sample(int dist) { return dist == D_F64U || dist == D_F64N ? 2 : 1; }
 inline uint64_t sample_limit(int dist) { return PERIOD / words_per_sample(dist); }
 
+// Philox2x32-10 keys with one 32-bit word: its seeds must be below 2^32.
+inline bool seed_ok(int gen, uint64_t seed) { return gen != G_PHILOX2X32 || seed <= 0xFFFFFFFFull; }
+
 // Launch knobs.  0 means "choose automatically".
 struct LaunchCfg {
     uint32_t wg_size;   // threads per workgroup (multiple of 64, <= 512)

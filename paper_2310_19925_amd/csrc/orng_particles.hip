@@ -93,10 +93,11 @@ using namespace orng;
 extern "C" int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particles,
                                      uint32_t draws, uint32_t ctr0, uint32_t n_iters,
                                      void *d_out, void *stream) {
-    if (gen < ORNG_PHILOX4X32_10 || gen > ORNG_SQUARES64 || draws < 1 || draws > 16)
+    if (gen < ORNG_PHILOX4X32_10 || gen > ORNG_PHILOX2X32 || draws < 1 || draws > 16)
         return ORNG_EINVAL;
     if (n_iters && (uint64_t)ctr0 + n_iters - 1 > 0xFFFFFFFFull) return ORNG_ERANGE;
     if (n_particles && seed0 + (n_particles - 1) < seed0) return ORNG_ERANGE;
+    if (n_particles && !seed_ok(gen, seed0 + (n_particles - 1))) return ORNG_ERANGE;
     if (!n_particles || !n_iters) return ORNG_OK;
     if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 3u)) return ORNG_EINVAL;
     PartArgs a;
@@ -125,6 +126,7 @@ extern "C" int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particl
     case G_TF2X64_13: kern = ORNG_PK(G_TF2X64_13); break;
     case G_TYCHE_I: kern = ORNG_PK(G_TYCHE_I); break;
     case G_SQUARES64: kern = ORNG_PK(G_SQUARES64); break;
+    case G_PHILOX2X32: kern = ORNG_PK(G_PHILOX2X32); break;
     default: kern = ORNG_PK(G_TYCHE); break;
     }
 #undef ORNG_PK

@@ -170,6 +170,7 @@ static void *range_units_kernel(int gen) {
     case G_TF2X64_13: return reinterpret_cast<void *>(&k_range_units<G_TF2X64_13>);
     case G_TYCHE_I: return reinterpret_cast<void *>(&k_range_units<G_TYCHE_I>);
     case G_SQUARES64: return reinterpret_cast<void *>(&k_range_units<G_SQUARES64>);
+    case G_PHILOX2X32: return reinterpret_cast<void *>(&k_range_units<G_PHILOX2X32>);
     default: return reinterpret_cast<void *>(&k_range_units<G_TYCHE>);
     }
 }
@@ -184,6 +185,7 @@ static void *range_kernel(int gen) {
     case G_TF2X64_13: return reinterpret_cast<void *>(&k_range<G_TF2X64_13>);
     case G_TYCHE_I: return reinterpret_cast<void *>(&k_range<G_TYCHE_I>);
     case G_SQUARES64: return reinterpret_cast<void *>(&k_range<G_SQUARES64>);
+    case G_PHILOX2X32: return reinterpret_cast<void *>(&k_range<G_PHILOX2X32>);
     default: return reinterpret_cast<void *>(&k_range<G_TYCHE>);
     }
 }
@@ -195,7 +197,7 @@ using namespace orng;
 extern "C" int orng_fill_range(int gen, uint64_t seed, uint32_t ctr0, uint32_t n_streams,
                                uint64_t offset, uint64_t per_stream, int32_t lo, int32_t hi,
                                int32_t *d_out, void *stream) {
-    if (gen < 0 || gen >= NGEN || lo >= hi) return ORNG_EINVAL;
+    if (gen < 0 || gen >= NGEN || lo >= hi || !seed_ok(gen, seed)) return ORNG_EINVAL;
     const uint64_t lim = PERIOD / 2;
     if (offset > lim || per_stream > lim - offset) return ORNG_ERANGE;
     if (n_streams && (uint64_t)ctr0 + n_streams - 1 > 0xFFFFFFFFull) return ORNG_ERANGE;

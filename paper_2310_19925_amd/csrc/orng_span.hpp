@@ -211,12 +211,13 @@ __device__ __forceinline__ void process_span_any(int gen, int dist, const KeySch
         ORNG_CASE(6, 0) ORNG_CASE(6, 1) ORNG_CASE(6, 2) ORNG_CASE(6, 3)
         ORNG_CASE(7, 0) ORNG_CASE(7, 1) ORNG_CASE(7, 2) ORNG_CASE(7, 3)
         ORNG_CASE(8, 0) ORNG_CASE(8, 1) ORNG_CASE(8, 2) ORNG_CASE(8, 3)
+        ORNG_CASE(9, 0) ORNG_CASE(9, 1) ORNG_CASE(9, 2) ORNG_CASE(9, 3)
         default:
             if constexpr (F64N) {
                 switch (gen * NDIST + dist) {
                     ORNG_CASE(0, 4) ORNG_CASE(1, 4) ORNG_CASE(2, 4) ORNG_CASE(3, 4)
                     ORNG_CASE(4, 4) ORNG_CASE(5, 4) ORNG_CASE(6, 4) ORNG_CASE(7, 4)
-                    ORNG_CASE(8, 4)
+                    ORNG_CASE(8, 4) ORNG_CASE(9, 4)
                     default: break;
                 }
             }

@@ -80,6 +80,12 @@ static const uint32_t kDefaultTable[NGEN * NDIST][8] = {
         {256, 2, 8192, 1, 128, 16, 1, 0},
         {64, 4, 0, 1, 512, 8, 1, 0},
         {512, 4, 8192, 1, 256, 16, 1, 0},
+        // Philox2x32-10
+        {64, 4, 0, 2, 512, 8, 1, 0},
+        {64, 4, 0, 2, 512, 8, 1, 0},
+        {512, 2, 8192, 1, 128, 16, 1, 0},
+        {128, 4, 0, 2, 512, 8, 1, 0},
+        {512, 8, 8192, 1, 256, 16, 1, 4},
 };
 
 static Tuned default_tuned(int gen, int dist) {

@@ -12,7 +12,7 @@ from __future__ import annotations
 import numpy as np
 
 GEN_NAMES = ["philox4x32_10", "threefry4x32_20", "threefry2x64_20", "squares32", "tyche",
-             "threefry4x32_13", "threefry2x64_13", "tyche_i", "squares64"]
+             "threefry4x32_13", "threefry2x64_13", "tyche_i", "squares64", "philox2x32_10"]
 DIST_NAMES = ["u32", "f32_uniform", "f32_normal", "f64_uniform", "f64_normal"]
 PERIOD = 1 << 32
 

@@ -44,7 +44,8 @@ def test_host_only_calls_without_gpu():
     # argument validation happens before any device work
     lib.orng_fill.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
                               ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
-    assert lib.orng_fill(9, 0, 1, 1, 0, 4, None, None) == -1
+    assert lib.orng_fill(10, 0, 1, 1, 0, 4, None, None) == -1
+    assert lib.orng_fill(9, 0, 2**32, 1, 0, 4, None, None) == -1  # 32-bit key
     assert lib.orng_fill(0, 0, 1, 1, 2**32, 1, None, None) == -2
     assert lib.orng_fill(0, 0, 1, 1, 0, 0, None, None) == 0
     assert lib.orng_fill(0, 0, 1, 1, 0, 4, None, None) == -1

@@ -20,11 +20,12 @@ def R():
     return orng
 
 
-def _random_batch(rng, m, max_log2=14, gens=range(9), dists=range(3)):
+def _random_batch(rng, m, max_log2=14, gens=range(10), dists=range(3)):
     L = np.maximum(1, np.floor(2.0 ** (max_log2 * rng.random(m)))).astype(np.int64)
     gen = rng.choice(list(gens), m)
     dist = rng.choice(list(dists), m)
     seed = rng.integers(0, 2**63, m, dtype=np.int64).astype(np.uint64) * 2 + 1
+    seed = np.where(gen == 9, seed & np.uint64(0xFFFFFFFF), seed)  # Philox2x32: 32-bit keys
     ctr = rng.integers(0, 2**32, m, dtype=np.uint64)
     off = np.floor(rng.random(m) * (2**32 - L + 1)).astype(np.uint64)
     off[: m // 10] = rng.integers(0, 64, m // 10)           # near the stream start
@@ -99,7 +100,7 @@ def test_batched_tyche_and_single_word_requests(R, O):
 def test_batched_errors(R):
     buf = torch.empty(64, dtype=torch.int32, device="cuda")
     good = R.make_requests(0, 0, 1, 1, 0, 16, buf.data_ptr())
-    bad = R.make_requests([0, 9], 0, 1, 1, 0, 16, buf.data_ptr())
+    bad = R.make_requests([0, 10], 0, 1, 1, 0, 16, buf.data_ptr())
     R.orng_fill_batched(good)
     with pytest.raises(R.OrngError) as e:
         R.orng_fill_batched(bad)
@@ -190,7 +191,7 @@ def test_autotune_writes_cache_and_keeps_results(R, O, tmp_path):
     path = str(tmp_path / "tune.txt")
     R.orng_autotune(0, 1, path)
     text = open(path).read()
-    assert text.startswith("#") and len(text.strip().split("\n")) == 1 + 9 * 5
+    assert text.startswith("#") and len(text.strip().split("\n")) == 1 + 10 * 5
     R.orng_tune_load(path)
     rng = np.random.default_rng(6)
     _run_and_check(R, O, *_random_batch(rng, 100, gens=[0], dists=[1]))

@@ -46,7 +46,7 @@ def test_concurrent_fills_and_batched_calls(R, O):
         rng = np.random.default_rng(100 + i)
         with torch.cuda.stream(s):
             for r in range(rounds):
-                gen, dist = int(rng.integers(0, 9)), int(rng.integers(0, 3))
+                gen, dist = int(rng.integers(0, 10)), int(rng.integers(0, 3))
                 off, n = int(rng.integers(0, 1000)), int(rng.integers(1, 200_000))
                 out = torch.empty(n, dtype=torch.int32, device="cuda")
                 R.orng_fill(gen, dist, 1000 * i + r, r, off, n, out, s)
@@ -78,9 +78,11 @@ def test_concurrent_submitters_share_one_server(R, O):
     def work(i):
         rng = np.random.default_rng(200 + i)
         for r in range(30):
-            q = dict(gen=int(rng.integers(0, 9)), dist=int(rng.integers(0, 4)),
+            q = dict(gen=int(rng.integers(0, 10)), dist=int(rng.integers(0, 4)),
                      seed=int(rng.integers(0, 2**63)), ctr=int(rng.integers(0, 2**32)),
                      offset=int(rng.integers(0, 2**20)), n=int(rng.integers(1, 100_000)))
+            if q["gen"] == 9:
+                q["seed"] &= 0xFFFFFFFF  # Philox2x32 keys with 32 bits
             t = R.orng_serve_submit(srv, **q)
             res = R.orng_serve_wait(srv, t)
             k = 2 if q["dist"] == 3 else 1

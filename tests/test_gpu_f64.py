@@ -29,6 +29,8 @@ def _case(R, O, gen, seed, ctr, off, n, pad=0, dist=F64):
     16-byte grid."""
     print("case gen=%d dist=%d seed=%d ctr=%d off=%d n=%d pad=%d"
           % (gen, dist, seed, ctr, off, n, pad), flush=True)
+    if gen == 9:
+        seed &= 0xFFFFFFFF  # Philox2x32 keys with 32 bits
     buf = torch.full((n + pad + 2,), -1, dtype=torch.int64, device="cuda")
     R.orng_fill(gen, dist, seed, ctr, off, n, buf[pad:pad + n])
     torch.cuda.synchronize()
@@ -40,7 +42,7 @@ def _case(R, O, gen, seed, ctr, off, n, pad=0, dist=F64):
 
 
 @pytest.mark.parametrize("dist", F64S)
-@pytest.mark.parametrize("gen", range(9))
+@pytest.mark.parametrize("gen", range(10))
 def test_f64_fill_parity(R, O, gen, dist):
     n = 3 * 8192 + 2 * 517 + 1
     _case(R, O, gen, 0x0123456789ABCDEF, 7, 0, n, dist=dist)
@@ -52,7 +54,7 @@ def test_f64_fill_parity(R, O, gen, dist):
 
 
 @pytest.mark.parametrize("dist", F64S)
-@pytest.mark.parametrize("gen", range(9))
+@pytest.mark.parametrize("gen", range(10))
 def test_f64_fill_multi(R, O, gen, dist):
     for n_streams, off, per in [(1000, 3, 5), (7, 1, 20001)]:
         out = torch.empty(n_streams * per, dtype=torch.int64, device="cuda")
@@ -68,7 +70,7 @@ def test_f64_bulk_sampled(R, O, dist):
     n = 1 << 29
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     rng = np.random.default_rng(12)
-    for gen in range(9):
+    for gen in range(10):
         print("bulk gen=%d dist=%d" % (gen, dist), flush=True)
         R.orng_fill(gen, dist, 0xFEED, 1, 0, n, out)
         torch.cuda.synchronize()
@@ -88,9 +90,11 @@ def _mixed_requests(rng, m, buf_words):
         k = 2 if dist in F64S else 1
         off_words += k - off_words % k  # 8-byte aligned doubles, 4-byte words
         off_words += int(rng.integers(0, 3)) * k
-        rows.append(dict(gen=int(rng.integers(0, 9)), dist=dist,
+        rows.append(dict(gen=int(rng.integers(0, 10)), dist=dist,
                          seed=int(rng.integers(0, 2**63)), ctr=int(rng.integers(0, 2**32)),
                          offset=int(rng.integers(0, 2**32 // k - n)), n=n, at=off_words))
+        if rows[-1]["gen"] == 9:
+            rows[-1]["seed"] &= 0xFFFFFFFF  # Philox2x32 keys with 32 bits
         off_words += n * k
     assert off_words < buf_words
     return rows

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-GENS = range(9)
+GENS = range(10)
 DISTS = range(3)
 
 
@@ -36,11 +36,18 @@ def bits(a):
     return np.ascontiguousarray(a).view(np.uint32)
 
 
+def key32(gen, seed):
+    """Philox2x32-10 (generator 9) takes seeds below 2^32: its tests use the
+    low word of the seed the other generators take."""
+    return seed & 0xFFFFFFFF if gen == 9 else seed
+
+
 def _case(R, O, gen, dist, seed, ctr, off, n, pad=0):
     """Fill through the C-ABI into a buffer starting `pad` words into an
     allocation (pad != 0 makes the output misaligned w.r.t. 16 bytes)."""
     print("case gen=%d dist=%d seed=%d ctr=%d off=%d n=%d pad=%d" % (gen, dist, seed, ctr, off, n,
                                                                     pad), flush=True)
+    seed = key32(gen, seed)
     buf = torch.full((n + pad + 4,), -1, dtype=torch.int32, device="cuda")
     out = buf[pad:pad + n]
     R.orng_fill(gen, dist, seed, ctr, off, n, out)
@@ -82,8 +89,12 @@ def test_fill_tiny_and_edges(R, O, gen):
 def test_fill_errors(R):
     out = torch.empty(16, dtype=torch.int32, device="cuda")
     with pytest.raises(R.OrngError) as e:
-        R.orng_fill(9, 0, 1, 1, 0, 4, out)
+        R.orng_fill(10, 0, 1, 1, 0, 4, out)
     assert e.value.status == R.EINVAL
+    with pytest.raises(R.OrngError) as e:
+        R.orng_fill(9, 0, 2**32, 1, 0, 4, out)  # Philox2x32 keys with 32 bits
+    assert e.value.status == R.EINVAL
+    R.orng_fill(9, 0, 2**32 - 1, 1, 0, 4, out)
     with pytest.raises(R.OrngError) as e:
         R.orng_fill(0, 5, 1, 1, 0, 4, out)
     assert e.value.status == R.EINVAL
@@ -123,7 +134,7 @@ def test_fill_multi_parity(R, O, gen, dist):
         assert np.array_equal(as_u32(out), bits(ref)), (n_streams, off, per)
 
 
-@pytest.mark.parametrize("gen", [0, 3, 4])
+@pytest.mark.parametrize("gen", [0, 3, 4, 9])
 def test_launch_geometry_invariance(R, O, gen):
     """Results do not depend on workgroup size, span length, grid size or
     store kind (paper section 4: unique streams regardless of thread count)."""
@@ -152,6 +163,7 @@ def test_bulk_config_sampled(R, O):
                           16384 * np.arange(1, 40)]).astype(np.int64)
     idx = torch.from_numpy(pos).cuda()
     for gen in GENS:
+        seed = key32(gen, inputs.bulk_seed())
         for dist in DISTS:
             print("bulk gen=%d dist=%d" % (gen, dist), flush=True)
             R.orng_fill(gen, dist, seed, 0, 0, n, out)
@@ -237,7 +249,7 @@ def test_grid_stride_sweep(R, O, gen):
     distributions from an odd offset into an output off the 16-byte grid, and
     a multi-stream fill whose waves cross stream boundaries, element by
     element against the oracle."""
-    seed = 0x9E3779B97F4A7C15
+    seed = key32(gen, 0x9E3779B97F4A7C15)
     n = (1 << 20) + 2333
     try:
         for cap in (1, 7):

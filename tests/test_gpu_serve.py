@@ -33,9 +33,11 @@ def _random_reqs(rng, m, lo=10, hi=16):
     out = []
     for _ in range(m):
         n = int(2 ** (lo + (hi - lo) * rng.random()))
-        out.append(dict(gen=int(rng.integers(0, 9)), dist=int(rng.integers(0, 3)),
+        out.append(dict(gen=int(rng.integers(0, 10)), dist=int(rng.integers(0, 3)),
                         seed=int(rng.integers(0, 2**63)), ctr=int(rng.integers(0, 2**32)),
                         offset=int(rng.integers(0, 2**32 - n)), n=n))
+        if out[-1]["gen"] == 9:
+            out[-1]["seed"] &= 0xFFFFFFFF  # Philox2x32 keys with 32 bits
     return out
 
 
@@ -144,7 +146,10 @@ def test_serve_errors(R):
             R.orng_serve_submit(srv, 0, 0, 1, 1, 0, 1 << 20)  # 4 MiB > 1 MiB arena
         assert e.value.status == R.ENOMEM
         with pytest.raises(R.OrngError) as e:
-            R.orng_serve_submit(srv, 9, 0, 1, 1, 0, 16)
+            R.orng_serve_submit(srv, 10, 0, 1, 1, 0, 16)
+        assert e.value.status == R.EINVAL
+        with pytest.raises(R.OrngError) as e:
+            R.orng_serve_submit(srv, 9, 0, 2**32, 1, 0, 16)
         assert e.value.status == R.EINVAL
         with pytest.raises(R.OrngError) as e:
             R.orng_serve_submit(srv, 0, 0, 1, 1, 2**32 - 4, 16)
@@ -193,7 +198,7 @@ def test_serve_submit_many_and_release_many(R, O):
         assert R.orng_serve_release_many(srv, tickets) == 50
         st = R.orng_serve_stats(srv)
         assert st["released"] == 50 and st["completed"] == 50
-        bad = R.make_requests([0, 9], 0, 1, 1, 0, 16, 0)
+        bad = R.make_requests([0, 10], 0, 1, 1, 0, 16, 0)
         with pytest.raises(R.OrngError) as e:
             R.orng_serve_submit_many(srv, bad)
         assert e.value.status == R.EINVAL

@@ -48,6 +48,7 @@ def test_fill_validation(L):
     assert L.orng_fill(0, 0, 1, 1, 2**32 + 1, 0, FAKE, None) == ERANGE
     assert L.orng_fill(0, 0, 1, 1, 0, 4, FAKE + 2, None) == EINVAL
     assert L.orng_fill(0, 0, 1, 1, 0, 4, None, None) == EINVAL
+    assert L.orng_fill(9, 0, 2**32, 1, 0, 4, FAKE, None) == EINVAL   # Philox2x32: 32-bit key
     assert L.orng_fill(0, 0, 1, 1, 2**32, 0, None, None) == 0
 
 
@@ -56,7 +57,8 @@ def test_fill_multi_validation(L):
     assert L.orng_fill_multi(0, 0, 1, 2**32 - 3, 3, 2**32 - 1, 2, FAKE, None) == ERANGE
     assert L.orng_fill_multi(0, 0, 1, 0, 0, 0, 4, None, None) == 0
     assert L.orng_fill_multi(0, 0, 1, 0, 5, 0, 0, None, None) == 0
-    assert L.orng_fill_multi(9, 0, 1, 0, 5, 0, 4, FAKE, None) == EINVAL
+    assert L.orng_fill_multi(10, 0, 1, 0, 5, 0, 4, FAKE, None) == EINVAL
+    assert L.orng_fill_multi(9, 0, 2**32, 0, 5, 0, 4, FAKE, None) == EINVAL  # 32-bit key
     assert L.orng_fill_multi(0, 3, 1, 0, 2, 2**31 - 1, 2, FAKE, None) == ERANGE
     assert L.orng_fill_multi(0, 3, 1, 0, 2, 0, 2, FAKE + 4, None) == EINVAL
 
@@ -88,7 +90,8 @@ def test_bd2_validation(L):
 
 
 def test_particle_streams_validation(L):
-    assert L.orng_particle_streams(9, 0, 10, 3, 0, 1, FAKE, None) == EINVAL
+    assert L.orng_particle_streams(10, 0, 10, 3, 0, 1, FAKE, None) == EINVAL
+    assert L.orng_particle_streams(9, 2**32 - 9, 10, 3, 0, 1, FAKE, None) == ERANGE
     assert L.orng_particle_streams(0, 0, 10, 0, 0, 1, FAKE, None) == EINVAL
     assert L.orng_particle_streams(0, 0, 10, 17, 0, 1, FAKE, None) == EINVAL
     assert L.orng_particle_streams(0, 0, 10, 3, 2**32 - 1, 2, FAKE, None) == ERANGE
@@ -118,7 +121,7 @@ def _reqs(rows):
 def test_batched_validation_rejects_whole_batch(L, fn):
     f = getattr(L, fn)
     cases = [
-        ([(0, 0, 0, 16, FAKE, 0), (9, 0, 0, 16, FAKE, 0)], EINVAL),     # bad generator
+        ([(0, 0, 0, 16, FAKE, 0), (10, 0, 0, 16, FAKE, 0)], EINVAL),    # bad generator
         ([(0, 5, 0, 16, FAKE, 0)], EINVAL),                              # bad distribution
         ([(0, 0, 0, 16, FAKE, 1)], EINVAL),                              # reserved flags
         ([(0, 0, 2**32 - 8, 16, FAKE, 0)], ERANGE),                      # past the period
@@ -136,6 +139,15 @@ def test_batched_validation_rejects_whole_batch(L, fn):
     assert f(None, 3, None) == EINVAL
 
 
+@pytest.mark.parametrize("fn", ["orng_fill_batched", "orng_fill_each", "orng_fill_batched_noalloc"])
+def test_batched_rejects_a_64_bit_philox2x32_seed(L, fn):
+    f = getattr(L, fn)
+    f.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p]
+    r = _reqs([(0, 0, 0, 16, FAKE, 0), (9, 0, 0, 16, FAKE, 0)])
+    r[1]["seed"] = 2**32
+    assert f(r.ctypes.data, r.size, None) == EINVAL
+
+
 @pytest.mark.parametrize("fn", ["orng_fill_batched", "orng_fill_each"])
 def test_batched_validation_reports_the_first_bad_request(L, fn):
     """Large lists are validated in parallel ranges; the status returned is
@@ -147,7 +159,7 @@ def test_batched_validation_reports_the_first_bad_request(L, fn):
         r = _reqs(rows)
         for (i, what) in (first, second):
             if what == 9:
-                r[i]["gen"] = 9
+                r[i]["gen"] = 10
             else:
                 r[i]["offset"] = what
         assert f(r.ctypes.data, r.size, None) == want
@@ -175,12 +187,12 @@ def test_launch_knob_validation(L):
 def test_tune_table_loader(L, tmp_path):
     assert L.orng_tune_load(str(tmp_path / "missing.txt").encode()) == ENOENT
     bad = tmp_path / "bad.txt"
-    bad.write_text("# header\n0 0 100 4 0 1 256 4 1 0\n9 0 256 4 0 1 256 4 1 0\nnot numbers\n")
+    bad.write_text("# header\n0 0 100 4 0 1 256 4 1 0\n10 0 256 4 0 1 256 4 1 0\nnot numbers\n")
     assert L.orng_tune_load(str(bad).encode()) == EINVAL  # no valid line
     good = tmp_path / "good.txt"
     good.write_text("# header\n0 0 256 2 0 2 256 4 1 0\n4 1 256 64 0 2 256 1 1 0\n")
     assert L.orng_tune_load(str(good).encode()) == 0
-    assert L.orng_autotune(9, 0, None) == EINVAL
+    assert L.orng_autotune(10, 0, None) == EINVAL
     assert L.orng_autotune(0, 5, None) == EINVAL
 
 
@@ -200,7 +212,8 @@ def test_serve_create_validation(L):
 
 
 def test_fill_range_validation(L):
-    assert L.orng_fill_range(9, 0, 0, 1, 0, 4, 0, 10, FAKE, None) == EINVAL
+    assert L.orng_fill_range(10, 0, 0, 1, 0, 4, 0, 10, FAKE, None) == EINVAL
+    assert L.orng_fill_range(9, 2**32, 0, 1, 0, 4, 0, 10, FAKE, None) == EINVAL
     assert L.orng_fill_range(-1, 0, 0, 1, 0, 4, 0, 10, FAKE, None) == EINVAL
     assert L.orng_fill_range(0, 0, 0, 1, 0, 4, 10, 10, FAKE, None) == EINVAL
     assert L.orng_fill_range(0, 0, 0, 1, 0, 4, 11, 10, FAKE, None) == EINVAL

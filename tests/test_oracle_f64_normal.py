@@ -148,7 +148,7 @@ def test_normal_pair_against_decimal(O, PI):
     assert (z0, z1) == (0.0, 0.0) and math.copysign(1, z0) == 1
 
 
-@pytest.mark.parametrize("gen", range(9))
+@pytest.mark.parametrize("gen", range(10))
 def test_f64_normal_layout(O, gen):
     """Sample p is member p mod 2 of the pair made from words 4(p/2)..4(p/2)+3."""
     seed, ctr, off, n = 0xABCDEF, 3, 1001, 3001

@@ -30,7 +30,7 @@ def test_tyche_micro_stream_is_the_textbook_instance(O):
 
 def test_ranges(O):
     O.particle_streams(0, 0, 2, 16, 2**32 - 1, 1)
-    for args in [(0, 0, 2, 17, 0, 1), (0, 0, 2, 0, 0, 1), (9, 0, 2, 3, 0, 1)]:
+    for args in [(0, 0, 2, 17, 0, 1), (0, 0, 2, 0, 0, 1), (10, 0, 2, 3, 0, 1)]:
         with pytest.raises(ValueError):
             O.particle_streams(*args)
     with pytest.raises(ValueError):

@@ -26,10 +26,11 @@ def _mixed_batch(rng, m, max_log2=14):
     float64 requests on 8-byte boundaries, the rest at any word."""
     L = np.maximum(1, np.floor(2.0 ** (max_log2 * rng.random(m)))).astype(np.int64)
     L[rng.choice(m, max(1, m // 50), replace=False)] = 0
-    gen = rng.integers(0, 9, m)
+    gen = rng.integers(0, 10, m)
     dist = rng.integers(0, 5, m)
     k = np.where(dist >= 3, 2, 1)
     seed = rng.integers(0, 2**63, m, dtype=np.int64).astype(np.uint64) * 2 + 1
+    seed = np.where(gen == 9, seed & np.uint64(0xFFFFFFFF), seed)  # Philox2x32: 32-bit keys
     ctr = rng.integers(0, 2**32, m, dtype=np.uint64)
     lim = np.where(k == 2, 2**31, 2**32)
     off = np.floor(rng.random(m) * (lim - L + 1)).astype(np.uint64)
