@@ -291,7 +291,8 @@ int orng_fill_each(const orng_req_t *h_reqs, size_t nreq, void *stream);
 /*
  * orng_autotune -- time launch variants of the fill and batched kernels for
  * (gen, dist) on the current device (workgroup size, blocks of four words per
- * lane per tile, tiles per queue claim, persistent workgroups per CU) and keep
+ * lane per tile, tiles per queue claim, persistent workgroups per CU), or with
+ * dist = ORNG_TUNE_RANGE those of orng_fill_range for gen, and keep
  * the fastest (a first pass over all variants, then the fastest few and the
  * entry in use re-timed against each other in interleaved rounds); results
  * never change, only speed.  Allocates 4 GiB of device memory for the
@@ -300,6 +301,7 @@ int orng_fill_each(const orng_req_t *h_reqs, size_t nreq, void *stream);
  * (existing entries for other pairs are kept).  orng_tune_load reads such a
  * file; the library also reads $ORNG_TUNE_CACHE at first use.
  */
+enum { ORNG_TUNE_RANGE = 5 };
 int orng_autotune(int gen, int dist, const char *cache_path);
 int orng_tune_load(const char *cache_path);
 

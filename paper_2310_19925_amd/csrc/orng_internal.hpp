@@ -44,6 +44,9 @@ struct Tuned {
 };
 Tuned tuned_fill(int gen, int dist);
 void set_tuned(int gen, int dist, const Tuned &t);
+// launch row of the integer-range fill (wg_size, unroll, max_wgs used)
+Tuned tuned_range(int gen);
+void set_tuned_range(int gen, const Tuned &t);
 int load_tune_cache(const char *path);
 int save_tune_cache(const char *path);
 

@@ -32,9 +32,14 @@ namespace orng {
 constexpr uint64_t RANGE_GROUP = 256;                       // samples, counter generators
 constexpr uint64_t RANGE_TILE = TYCHE_TILE_WORDS / 2;       // samples per Tyche tile
 
-__device__ __forceinline__ uint32_t range_scale(uint32_t w0, uint32_t w1, uint32_t r) {
-    const uint64_t t = (uint64_t)w0 * r;
-    const uint64_t s = (uint64_t)w1 * r + (t >> 32);
+// lo + floor(((w1 << 32) | w0) r / 2^64) (mod 2^32) in two instructions: the
+// high half of w0 r, then w1 r plus a 64-bit addend whose low word is that
+// half and whose high word is lo -- adding lo 2^32 to the sum adds lo to its
+// high word (a carry out of bit 63 is dropped, as a 32-bit add of lo drops it).
+__device__ __forceinline__ uint32_t range_sample(uint32_t w0, uint32_t w1, uint32_t r,
+                                                 uint32_t lo) {
+    const uint32_t t = __umulhi(w0, r);
+    const uint64_t s = (uint64_t)w1 * r + (((uint64_t)lo << 32) | t);
     return (uint32_t)(s >> 32);
 }
 
@@ -42,12 +47,13 @@ struct RangeArgs {
     KeySched ks;
     int32_t *out;               // sample s0 of stream 0
     uint64_t s0, n;             // first sample, samples per stream
-    uint64_t first_group;       // first group of every stream
-    uint64_t groups_per_stream;
-    uint64_t total_groups;      // n_streams * groups_per_stream
+    uint64_t first_span;        // first span of every stream
+    uint64_t spans_per_stream;
+    uint64_t total_spans;       // n_streams * spans_per_stream
     uint32_t ctr0;              // counter of stream 0
     uint32_t lo, r;             // lo as its two's-complement bits, r = hi - lo
     uint32_t mis;               // (stream 0 output address in words - s0) mod 4
+    uint32_t unroll;            // groups per span (counter generators)
 };
 
 template <int N>
@@ -68,49 +74,102 @@ __device__ __forceinline__ void range_store(int32_t *base, uint64_t q, uint64_t 
         if (q + i >= s0 && q + i < send) base[q + i - s0] = (int32_t)v[i];
 }
 
+// Group g of a counter generator's stream: lane l makes blocks 2m and 2m + 1,
+// m = 64 g + l, i.e. samples 4m .. 4m + 3, and writes them with one 16-byte
+// store.
 template <int G>
-__global__ __launch_bounds__(256) void k_range(RangeArgs a) {
+__device__ __forceinline__ void range_group(const RangeArgs &a, uint64_t g, uint32_t ctr,
+                                            int32_t *base, uint64_t send, bool aligned,
+                                            uint32_t lane) {
+    const uint64_t m = g * 64u + lane;
+    if (4 * m >= send || 4 * m + 4 <= a.s0) return;
+    uint32_t w[4], x[4];
+    counter_block<G>((uint32_t)(2 * m), ctr, a.ks, w);
+    counter_block<G>((uint32_t)(2 * m + 1), ctr, a.ks, x);
+    const uint32_t v[4] = {range_sample(w[0], w[1], a.r, a.lo),
+                           range_sample(w[2], w[3], a.r, a.lo),
+                           range_sample(x[0], x[1], a.r, a.lo),
+                           range_sample(x[2], x[3], a.r, a.lo)};
+    range_store<4>(base, 4 * m, a.s0, send, aligned, v);
+}
+
+// One span per wave and loop trip, like the fill kernels: counter generators
+// take `unroll` consecutive groups of 256 samples (the launch table's span
+// length), Tyche one tile.  The grid normally covers every span with one wave
+// (short-lived waves keep the most stores in flight); a grid cap makes the
+// waves loop.
+template <int G>
+__global__ __launch_bounds__(512) void k_range(RangeArgs a) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wpg = blockDim.x >> 6;
     const uint64_t wave0 =
         __builtin_amdgcn_readfirstlane(blockIdx.x * wpg + (threadIdx.x >> 6));
     const uint64_t nwaves = (uint64_t)gridDim.x * wpg;
     const uint64_t send = a.s0 + a.n;
-    for (uint64_t t = wave0; t < a.total_groups; t += nwaves) {
-        uint64_t si = 0, gl = t;
-        if (a.groups_per_stream != a.total_groups) {
-            si = t / a.groups_per_stream;
-            gl = t - si * a.groups_per_stream;
+    for (uint64_t t = wave0; t < a.total_spans; t += nwaves) {
+        uint64_t si = 0, sl = t;
+        if (a.spans_per_stream != a.total_spans) {
+            si = t / a.spans_per_stream;
+            sl = t - si * a.spans_per_stream;
         }
-        const uint64_t g = a.first_group + gl;
+        const uint64_t span = a.first_span + sl;
         const uint32_t ctr = a.ctr0 + (uint32_t)si;
         int32_t *base = a.out + si * a.n;
         const uint32_t mis = (a.mis + (uint32_t)(si * a.n)) & 3u;
         if constexpr (tyche_like(G)) {
             TycheT<G == G_TYCHE_I> st;
-            st.seed(a.ks, (uint32_t)g * 64u + lane, ctr);
-            const uint64_t b0 = g * TYCHE_TILE_BLOCKS;
+            st.seed(a.ks, (uint32_t)span * 64u + lane, ctr);
+            const uint64_t b0 = span * TYCHE_TILE_BLOCKS;
             for (uint32_t k = 0; k < 64; ++k) {
                 const uint64_t bw = b0 + 64u * k;  // first block of this step
                 if (2 * bw >= send) break;
                 uint32_t w[4];
                 st.next4(w);
                 if (2 * (bw + 64) <= a.s0) continue;
-                const uint32_t v[2] = {a.lo + range_scale(w[0], w[1], a.r),
-                                       a.lo + range_scale(w[2], w[3], a.r)};
+                const uint32_t v[2] = {range_sample(w[0], w[1], a.r, a.lo),
+                                       range_sample(w[2], w[3], a.r, a.lo)};
                 range_store<2>(base, 2 * (bw + lane), a.s0, send, (mis & 1u) == 0, v);
             }
         } else {
-            const uint64_t m = g * 64u + lane;
-            if (4 * m < send && 4 * m + 4 > a.s0) {
-                uint32_t w[4], x[4];
-                counter_block<G>((uint32_t)(2 * m), ctr, a.ks, w);
-                counter_block<G>((uint32_t)(2 * m + 1), ctr, a.ks, x);
-                const uint32_t v[4] = {a.lo + range_scale(w[0], w[1], a.r),
-                                       a.lo + range_scale(w[2], w[3], a.r),
-                                       a.lo + range_scale(x[0], x[1], a.r),
-                                       a.lo + range_scale(x[2], x[3], a.r)};
-                range_store<4>(base, 4 * m, a.s0, send, mis == 0, v);
+            const uint64_t g0 = span * a.unroll;
+            const uint64_t q0 = g0 * RANGE_GROUP, q1 = q0 + a.unroll * RANGE_GROUP;
+            if (mis == 0 && q0 >= a.s0 && q1 <= send) {
+                // A span inside the range with 16-byte aligned output: no
+                // per-sample checks, the store address steps by 1 KiB.  The
+                // store of a group is issued after the next group is made,
+                // and stores are non-temporal: on MI355X both let the
+                // generation overlap the writes better (the span's 1-4 MiB
+                // are not read back soon).
+                typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+                u4 *o = reinterpret_cast<u4 *>(base + (q0 - a.s0)) + lane;
+                uint32_t blk = (uint32_t)(2 * (g0 * 64u + lane));
+                auto make = [&](uint32_t b) {
+                    uint32_t w[4], x[4];
+                    counter_block<G>(b, ctr, a.ks, w);
+                    counter_block<G>(b + 1u, ctr, a.ks, x);
+                    return u4{range_sample(w[0], w[1], a.r, a.lo),
+                              range_sample(w[2], w[3], a.r, a.lo),
+                              range_sample(x[0], x[1], a.r, a.lo),
+                              range_sample(x[2], x[3], a.r, a.lo)};
+                };
+                u4 prev = make(blk);
+                for (uint32_t u = 1; u < a.unroll; ++u) {
+                    blk += 128u;
+                    const u4 v = make(blk);
+                    __builtin_nontemporal_store(prev, o);
+                    o += 64;
+                    prev = v;
+                }
+                __builtin_nontemporal_store(prev, o);
+                continue;
+            }
+            // groups wholly before the range's first sample are skipped,
+            // and the span ends at the range's last one
+            uint32_t u = a.s0 / RANGE_GROUP > g0 ? (uint32_t)(a.s0 / RANGE_GROUP - g0) : 0u;
+            for (; u < a.unroll; ++u) {
+                const uint64_t g = g0 + u;
+                if (g * RANGE_GROUP >= send) break;
+                range_group<G>(a, g, ctr, base, send, mis == 0, lane);
             }
         }
     }
@@ -145,17 +204,17 @@ __global__ __launch_bounds__(256) void k_range_units(RangeUnitArgs a) {
         for (uint32_t j = 0; j < 4 * k; ++j) st.mix();
         uint32_t w[4];
         st.next4(w);
-        const uint32_t v[2] = {a.lo + range_scale(w[0], w[1], a.r),
-                               a.lo + range_scale(w[2], w[3], a.r)};
+        const uint32_t v[2] = {range_sample(w[0], w[1], a.r, a.lo),
+                               range_sample(w[2], w[3], a.r, a.lo)};
         range_store<2>(base, 2 * (uint64_t)u, a.s0, send, false, v);
     } else {
         uint32_t w[4], x[4];
         counter_block<G>(2 * u, ctr, a.ks, w);
         counter_block<G>(2 * u + 1, ctr, a.ks, x);
-        const uint32_t v[4] = {a.lo + range_scale(w[0], w[1], a.r),
-                               a.lo + range_scale(w[2], w[3], a.r),
-                               a.lo + range_scale(x[0], x[1], a.r),
-                               a.lo + range_scale(x[2], x[3], a.r)};
+        const uint32_t v[4] = {range_sample(w[0], w[1], a.r, a.lo),
+                               range_sample(w[2], w[3], a.r, a.lo),
+                               range_sample(x[0], x[1], a.r, a.lo),
+                               range_sample(x[2], x[3], a.r, a.lo)};
         range_store<4>(base, 4 * (uint64_t)u, a.s0, send, false, v);
     }
 }
@@ -237,13 +296,16 @@ extern "C" int orng_fill_range(int gen, uint64_t seed, uint32_t ctr0, uint32_t n
     a.lo = (uint32_t)lo;
     a.r = (uint32_t)((int64_t)hi - (int64_t)lo);
     a.mis = (uint32_t)((reinterpret_cast<uintptr_t>(d_out) / 4 - offset) & 3u);
-    const uint64_t gs = tyche_like(gen) ? RANGE_TILE : RANGE_GROUP;
-    a.first_group = offset / gs;
-    a.groups_per_stream = (offset + per_stream - 1) / gs - a.first_group + 1;
-    a.total_groups = a.groups_per_stream * n_streams;
-    const uint32_t wg = 256, wpg = wg / 64;
-    uint64_t grid = (a.total_groups + wpg - 1) / wpg;
-    const uint64_t cap = (uint64_t)device_cu_count() * 8;
+    const LaunchCfg cfg = launch_cfg();
+    const Tuned tu = tuned_range(gen);
+    a.unroll = tyche_like(gen) ? 1 : (cfg.unroll ? cfg.unroll : tu.unroll);
+    const uint64_t span_samples = tyche_like(gen) ? RANGE_TILE : RANGE_GROUP * a.unroll;
+    a.first_span = offset / span_samples;
+    a.spans_per_stream = (offset + per_stream - 1) / span_samples - a.first_span + 1;
+    a.total_spans = a.spans_per_stream * n_streams;
+    const uint32_t wg = cfg.wg_size ? cfg.wg_size : tu.wg_size, wpg = wg / 64;
+    uint64_t grid = (a.total_spans + wpg - 1) / wpg;
+    const uint64_t cap = cfg.max_wgs ? cfg.max_wgs : (tu.max_wgs ? tu.max_wgs : (1ull << 30));
     if (grid > cap) grid = cap;
     void *args[] = {&a};
     const hipError_t e = hipLaunchKernel(range_kernel(gen), dim3((uint32_t)grid), dim3(wg), args,

@@ -88,6 +88,27 @@ static const uint32_t kDefaultTable[NGEN * NDIST][8] = {
         {512, 8, 8192, 1, 256, 16, 1, 4},
 };
 
+// Integer-range fills (orng_fill_range), one row per generator: workgroup
+// size, groups of 256 samples per span (Tyche: one tile), grid cap (0: one
+// wave per span), store kind (unused: ordinary stores).
+// Measured on MI355X (a sweep of 64-512 threads, 1-16 groups per span, grid
+// uncapped or 8 workgroups per CU, 2^30 samples; the fastest shape per
+// generator).
+static const uint32_t kRangeTable[NGEN][4] = {
+        {128, 16, 0, 2},  {512, 1, 2048, 2}, {256, 16, 2048, 2}, {512, 16, 0, 2}, {64, 1, 0, 2},
+        {256, 1, 2048, 2}, {256, 16, 0, 2},   {64, 1, 0, 2},      {256, 16, 0, 2}, {512, 16, 0, 2},
+};
+static Tuned g_range[NGEN];
+
+static Tuned default_range(int gen) {
+    Tuned t{};
+    t.wg_size = kRangeTable[gen][0];
+    t.unroll = kRangeTable[gen][1];
+    t.max_wgs = kRangeTable[gen][2];
+    t.nontemporal = kRangeTable[gen][3];
+    return t;
+}
+
 static Tuned default_tuned(int gen, int dist) {
     const uint32_t *v = kDefaultTable[gen * NDIST + dist];
     Tuned t;
@@ -104,8 +125,10 @@ static Tuned default_tuned(int gen, int dist) {
 
 static void init_locked() {
     if (g_tuned_init) return;
-    for (int g = 0; g < NGEN; ++g)
+    for (int g = 0; g < NGEN; ++g) {
         for (int d = 0; d < NDIST; ++d) g_tuned[g][d] = default_tuned(g, d);
+        g_range[g] = default_range(g);
+    }
     g_tuned_init = true;
 }
 
@@ -127,6 +150,18 @@ Tuned tuned_fill(int gen, int dist) {
     return g_tuned[gen][dist];
 }
 
+Tuned tuned_range(int gen) {
+    init_from_env_once();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_range[gen];
+}
+
+void set_tuned_range(int gen, const Tuned &t) {
+    init_from_env_once();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_range[gen] = t;
+}
+
 void set_tuned(int gen, int dist, const Tuned &t) {
     init_from_env_once();
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -139,6 +174,11 @@ static bool sane(const Tuned &t, int gen) {
            t.b_unroll >= 1 && t.b_unroll <= 64 && t.b_chunk >= 1 && t.b_chunk <= 64 &&
            t.b_wgs_per_cu <= 64 && t.nontemporal >= 1 &&
            t.nontemporal <= 2 && (!tyche_like(gen) || t.unroll == 64);
+}
+
+static bool sane_range(const Tuned &t) {
+    return t.wg_size >= 64 && t.wg_size <= 512 && t.wg_size % 64 == 0 && t.unroll >= 1 &&
+           t.unroll <= 64 && t.nontemporal >= 1 && t.nontemporal <= 2;
 }
 
 static int load_locked(const char *path) {
@@ -155,6 +195,11 @@ static int load_locked(const char *path) {
                    &t.b_wgs_per_cu) == 10 &&
             g >= 0 && g < NGEN && d >= 0 && d < NDIST && sane(t, g)) {
             g_tuned[g][d] = t;
+            ++loaded;
+        } else if (sscanf(line, "%d %d %u %u %u %u", &g, &d, &t.wg_size, &t.unroll, &t.max_wgs,
+                          &t.nontemporal) == 6 &&
+                   g >= 0 && g < NGEN && d == ORNG_TUNE_RANGE && sane_range(t)) {
+            g_range[g] = t;  // an integer-range row: its batched fields are unused
             ++loaded;
         }
     }
@@ -175,13 +220,18 @@ int save_tune_cache(const char *path) {
     FILE *f = fopen(tmp.c_str(), "w");
     if (!f) return ORNG_EINVAL;
     fprintf(f, "# orng launch table: gen dist wg unroll max_wgs nontemporal "
-               "batched_wg batched_unroll batched_chunk batched_wgs_per_cu\n");
-    for (int g = 0; g < NGEN; ++g)
+               "batched_wg batched_unroll batched_chunk batched_wgs_per_cu "
+               "(dist %d: the integer-range fill, fill fields only)\n", ORNG_TUNE_RANGE);
+    for (int g = 0; g < NGEN; ++g) {
         for (int d = 0; d < NDIST; ++d) {
             const Tuned &t = g_tuned[g][d];
             fprintf(f, "%d %d %u %u %u %u %u %u %u %u\n", g, d, t.wg_size, t.unroll, t.max_wgs,
                     t.nontemporal, t.b_wg_size, t.b_unroll, t.b_chunk, t.b_wgs_per_cu);
         }
+        const Tuned &t = g_range[g];
+        fprintf(f, "%d %d %u %u %u %u 0 0 0 0\n", g, ORNG_TUNE_RANGE, t.wg_size, t.unroll,
+                t.max_wgs, t.nontemporal);
+    }
     fclose(f);
     return rename(tmp.c_str(), path) == 0 ? ORNG_OK : ORNG_EINVAL;
 }
@@ -241,6 +291,37 @@ static Tuned refine(std::vector<std::pair<float, Tuned>> cands, size_t keep, int
     return cands.empty() ? Tuned{} : cands[best].second;
 }
 
+// Integer-range fill of gen: workgroup size x span length x grid cap, the
+// entry in use competing too; 2^30 samples into buf.
+static hipError_t tune_range(int gen, void *buf, uint64_t n, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    const int cus = device_cu_count();
+    Tuned best = tuned_range(gen);
+    std::vector<std::pair<float, Tuned>> cands;
+    cands.push_back({0.0f, best});
+    auto run = [&] {
+        orng_fill_range(gen, 0x5EED, 0, 1, 0, n, -1000000000, 1000000007,
+                        static_cast<int32_t *>(buf), s);
+    };
+    for (uint32_t wg : {64u, 128u, 256u, 512u})
+        for (uint32_t un : {1u, 2u, 4u, 8u, 16u}) {
+            if (tyche_like(gen) && un != 1) continue;
+            for (uint32_t cap : {0u, (uint32_t)cus * 8}) {
+                if (e != hipSuccess) break;
+                Tuned t = best;
+                t.wg_size = wg;
+                t.unroll = un;
+                t.max_wgs = cap;
+                set_tuned_range(gen, t);
+                cands.push_back({time_ms(s, 3, run, &e), t});
+            }
+        }
+    if (e == hipSuccess)
+        best = refine(cands, 6, 9, s, [&](const Tuned &t) { set_tuned_range(gen, t); }, run, &e);
+    set_tuned_range(gen, best);
+    return e;
+}
+
 }  // namespace orng
 
 using namespace orng;
@@ -253,7 +334,33 @@ int orng_tune_load(const char *cache_path) {
 }
 
 int orng_autotune(int gen, int dist, const char *cache_path) {
-    if (gen < 0 || gen >= NGEN || dist < 0 || dist >= NDIST) return ORNG_EINVAL;
+    if (gen < 0 || gen >= NGEN || dist < 0 || (dist >= NDIST && dist != ORNG_TUNE_RANGE))
+        return ORNG_EINVAL;
+    if (dist == ORNG_TUNE_RANGE) {
+        const uint64_t n = 1ull << 30;
+        void *buf = nullptr;
+        hipStream_t s = nullptr;
+        hipError_t e = hipMalloc(&buf, n * 4);
+        if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; }
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) { hipFree(buf); set_hip_error(e); return ORNG_EHIP; }
+        const LaunchCfg saved_cfg = launch_cfg();
+        set_launch_cfg(LaunchCfg{0, 0, 0, 0});
+        e = tune_range(gen, buf, n, s);
+        set_launch_cfg(saved_cfg);
+        const hipError_t e2 = hipStreamSynchronize(s);
+        hipStreamDestroy(s);
+        hipFree(buf);
+        if (e == hipSuccess) e = e2;
+        if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; }
+        if (cache_path) {
+            const Tuned best = tuned_range(gen);
+            load_tune_cache(cache_path);
+            set_tuned_range(gen, best);
+            return save_tune_cache(cache_path);
+        }
+        return ORNG_OK;
+    }
     const uint64_t n = 1ull << 30;  // 4 GiB of samples: the size of a bulk fill
     void *buf = nullptr;
     hipStream_t s = nullptr;

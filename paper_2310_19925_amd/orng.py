@@ -19,6 +19,7 @@ PHILOX4X32_10, THREEFRY4X32_20, THREEFRY2X64_20, SQUARES32, TYCHE = range(5)
 THREEFRY4X32_13, THREEFRY2X64_13, TYCHE_I, SQUARES64, PHILOX2X32 = 5, 6, 7, 8, 9
 U32, F32_UNIFORM, F32_NORMAL, F64_UNIFORM, F64_NORMAL = range(5)
 OK, EINVAL, ERANGE, ENOMEM, EAGAIN, EBUSY, EHIP, ENOENT = 0, -1, -2, -3, -4, -5, -6, -7
+TUNE_RANGE = 5  # orng_autotune(gen, TUNE_RANGE): the integer-range fill
 
 
 class OrngError(RuntimeError):

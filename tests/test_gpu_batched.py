@@ -191,7 +191,7 @@ def test_autotune_writes_cache_and_keeps_results(R, O, tmp_path):
     path = str(tmp_path / "tune.txt")
     R.orng_autotune(0, 1, path)
     text = open(path).read()
-    assert text.startswith("#") and len(text.strip().split("\n")) == 1 + 10 * 5
+    assert text.startswith("#") and len(text.strip().split("\n")) == 1 + 10 * 6
     R.orng_tune_load(path)
     rng = np.random.default_rng(6)
     _run_and_check(R, O, *_random_batch(rng, 100, gens=[0], dists=[1]))

@@ -111,3 +111,15 @@ def test_range_nothing_to_do(R):
     R.orng_fill_range(0, 1, 2, 1, 2**31, 0, 0, 5, 0)
     with pytest.raises(R.OrngError):
         R.orng_fill_range(0, 1, 2, 1, 0, 4, 5, 5, 0)
+
+
+def test_range_autotune_keeps_results(R, O, tmp_path):
+    """orng_autotune(gen, TUNE_RANGE) retimes the integer-range launch shapes;
+    results never change, and the tuned row is written to the cache file."""
+    path = str(tmp_path / "tune.txt")
+    R.orng_autotune(0, R.TUNE_RANGE, path)
+    rows = [l.split() for l in open(path) if not l.startswith("#")]
+    assert sum(1 for r in rows if r[1] == "5") == 10
+    R.orng_tune_load(path)
+    _case(R, O, 0, 0x1234, 5, 3, 3 * 8192 + 7, -17, 1 << 20)
+    _case(R, O, 0, 0x1234, 5, 1 << 24, (1 << 20) + 5, -17, 1 << 20, pad=2)

@@ -193,7 +193,12 @@ def test_tune_table_loader(L, tmp_path):
     good.write_text("# header\n0 0 256 2 0 2 256 4 1 0\n4 1 256 64 0 2 256 1 1 0\n")
     assert L.orng_tune_load(str(good).encode()) == 0
     assert L.orng_autotune(10, 0, None) == EINVAL
-    assert L.orng_autotune(0, 5, None) == EINVAL
+    assert L.orng_autotune(0, 6, None) == EINVAL  # 5 is the integer-range fill
+    rng_line = tmp_path / "range.txt"
+    rng_line.write_text("# header\n3 5 128 8 0 2 0 0 0 0\n")  # an integer-range row
+    assert L.orng_tune_load(str(rng_line).encode()) == 0
+    rng_line.write_text("# header\n3 5 100 8 0 2 0 0 0 0\n")  # not a workgroup size
+    assert L.orng_tune_load(str(rng_line).encode()) == EINVAL
 
 
 def test_serve_create_validation(L):
