@@ -57,7 +57,9 @@ enum {
     ORNG_F32_UNIFORM = 1, /* (word >> 8) * 2^-24, in [0, 1) */
     ORNG_F32_NORMAL = 2,  /* Box-Muller, one member of a pair per sample */
     ORNG_F64_UNIFORM = 3, /* two words per sample: ((w1 << 32 | w0) >> 11) * 2^-53, in [0, 1) */
-    ORNG_F64_NORMAL = 4   /* float64 Box-Muller, pair m from the four words 4m..4m+3 */
+    ORNG_F64_NORMAL = 4,  /* float64 Box-Muller, pair m from the four words 4m..4m+3 */
+    ORNG_I32_RANGE = 5    /* int32 in [lo, hi) from the word pair 2p, 2p+1 (orng_fill_range);
+                             request records only: they carry the bounds */
 };
 
 /* status codes */
@@ -111,7 +113,8 @@ enum {
  * Arguments: gen, dist (enums above); d_out: device buffer of n samples
  * (n * 4 bytes, 4-byte aligned; n * 8 bytes, 8-byte aligned for the float64
  * distributions).
- * Errors: EINVAL (enum, NULL, alignment, a Philox2x32 seed of 2^32 or more),
+ * Errors: EINVAL (enum, NULL, alignment, a Philox2x32 seed of 2^32 or more;
+ *         ORNG_I32_RANGE too, which needs bounds: orng_fill_range),
  *         ERANGE (offset + n past the last sample: 2^32, or 2^31 for the
  *         float64 distributions).
  */
@@ -228,9 +231,15 @@ int orng_normal_pairs(const uint32_t *d_x0, const uint32_t *d_x1, uint64_t n, fl
                       float *d_z1, void *stream);
 
 /*
- * Fill request: the arguments of one orng_fill, as a record.  48 bytes.
- *   out   : device buffer of n * 4 bytes (caller-owned, 4-byte aligned)
- *   flags : reserved, must be 0
+ * Fill request: the arguments of one orng_fill, as a record.  56 bytes.
+ *   out    : device buffer of n samples (caller-owned): n * 4 bytes, 4-byte
+ *            aligned; n * 8 bytes, 8-byte aligned for the float64 distributions
+ *   flags  : reserved, must be 0
+ *   lo, hi : dist == ORNG_I32_RANGE only: the request is the single-stream
+ *            orng_fill_range(gen, seed, ctr, 1, offset, n, lo, hi, out), so
+ *            lo < hi, offsets and counts are in samples of two words (at
+ *            most 2^31 per stream) and out holds n int32; ignored for every
+ *            other distribution
  */
 typedef struct {
     uint64_t seed;
@@ -241,17 +250,21 @@ typedef struct {
     uint32_t gen;
     uint32_t dist;
     uint32_t flags;
+    int32_t lo;
+    int32_t hi;
 } orng_req_t;
 
 /*
  * orng_fill_batched -- every request r of h_reqs[0 .. nreq) is filled exactly
  * as orng_fill(r.gen, r.dist, r.seed, r.ctr, r.offset, r.n, r.out) would fill
- * it (each sample depends only on its own stream and position, section 3.1),
+ * it (orng_fill_range with r.lo, r.hi for ORNG_I32_RANGE; each sample depends
+ * only on its own stream and position, section 3.1),
  * in one persistent launch that pulls fixed-size tiles of all requests from a
  * device work queue; the launch is replayed from a captured hipGraph.
  * h_reqs is host memory, copied before the call returns.  Output ranges of
  * different requests must not overlap.  Requests with n == 0 are skipped.
- * Errors: EINVAL / ERANGE as orng_fill for the first bad request (nothing is
+ * Errors: EINVAL / ERANGE as orng_fill (orng_fill_range for ORNG_I32_RANGE:
+ *         EINVAL when lo >= hi) for the first bad request (nothing is
  *         enqueued then); ENOMEM if the batch needs more than 2^28 tiles or
  *         holds 2^32 or more requests.
  */
@@ -262,10 +275,10 @@ int orng_fill_batched(const orng_req_t *h_reqs, size_t nreq, void *stream);
  * allocate memory (code under stream capture, tight serving loops, harnesses
  * that forbid hipMalloc): the same results, the same generation kernels, and
  * no allocation of any kind by the call.  The batch's header, request table
- * (64 bytes per request) and tile map (4 bytes per tile) live in a fixed
- * device array of the library (about 24 MiB, held by every device the call
- * runs on until the process ends), and the rows are staged in a fixed host
- * array.  Limits: at most ORNG_NOALLOC_MAX_REQUESTS requests and
+ * (64 bytes per request, plus 8 for integer-range bounds) and tile map (4
+ * bytes per tile) live in a fixed device array of the library (about 25 MiB,
+ * held by every device the call runs on until the process ends), and the
+ * rows are staged in a fixed host array.  Limits: at most ORNG_NOALLOC_MAX_REQUESTS requests and
  * ORNG_NOALLOC_MAX_TILES tiles (a tile is 2,048 to 65,536 words at the
  * built-in launch shapes; any request with work needs at least one).
  * Behaviour: the call returns after the request rows are uploaded, which

@@ -9,8 +9,9 @@
 // tile; W = waves per workgroup, taken with the rest of the launch shape from
 // the (generator, distribution) pair holding most of the batch's words), and
 // a prefix sum gives every request its first tile number.  The header, the request table
-// and a tile -> request map are written into pinned staging and uploaded with
-// two copies into a device buffer whose layout is fixed for its capacity.
+// and a tile -> request map (and, for a batch with integer-range requests, a
+// table of their bounds) are written into pinned staging and uploaded with
+// two copies (three) into a device buffer whose layout is fixed for its capacity.
 // Device: a persistent grid pulls tiles from an atomic cursor in the header
 // (`chunk` tiles per pull), looks up the request of each tile in the map and
 // generates it with the same span code as the plain fill.  A static schedule
@@ -61,6 +62,7 @@ struct BatchView {
     BatchHdr *hdr;
     const DevReq *reqs;
     const uint32_t *map;
+    const uint32_t *bounds;  // request r: lo's bits at 2r, hi - lo at 2r + 1 (integer ranges)
 };
 
 __device__ __forceinline__ uint64_t bcast_lane0(uint64_t x) {
@@ -70,20 +72,28 @@ __device__ __forceinline__ uint64_t bcast_lane0(uint64_t x) {
 }
 
 // Generate spans j0, j0 + step, ... < W of tile t of the batch (wave-uniform).
-template <bool NT, bool F64N>
-__device__ __forceinline__ void run_tile(const DevReq *reqs, const uint32_t *map, uint64_t t,
-                                         uint32_t W, uint32_t j0, uint32_t step, uint32_t lane) {
-    const uint32_t r = map[t];
-    const DevReq q = reqs[r];
+// RNG: the variant with the integer-range cases, for batches that hold one.
+template <bool NT, bool F64N, bool RNG>
+__device__ __forceinline__ void run_tile(const BatchView &v, uint64_t t, uint32_t W, uint32_t j0,
+                                         uint32_t step, uint32_t lane) {
+    const uint32_t r = v.map[t];
+    const DevReq q = v.reqs[r];
     const KeySched ks = make_keysched(q.seed);
     const int gen = (int)(q.flags & 15u), dist = (int)((q.flags >> 4) & 15u);
+    uint32_t lo = 0, rr = 0;
+    if constexpr (RNG) {
+        if (dist == D_I32R) {
+            lo = v.bounds[2 * (uint64_t)r];
+            rr = v.bounds[2 * (uint64_t)r + 1];
+        }
+    }
     const uint64_t span0 = q.first_span + (t - q.tile_start) * W;
     for (uint32_t j = j0; j < W; j += step)
-        process_span_any<NT, F64N>(gen, dist, ks, q.ctr, q.out, q.p0, q.p0 + q.n, span0 + j,
-                                   q.unroll, (q.flags >> 8) & 3u, lane);
+        process_span_any<NT, F64N, RNG>(gen, dist, ks, q.ctr, q.out, q.p0, q.p0 + q.n,
+                                        span0 + j, q.unroll, (q.flags >> 8) & 3u, lane, lo, rr);
 }
 
-template <bool NT, bool F64N>
+template <bool NT, bool F64N, bool RNG>
 __global__ __launch_bounds__(512) void k_batched(BatchView v) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t total = v.hdr->total_tiles;
@@ -96,7 +106,7 @@ __global__ __launch_bounds__(512) void k_batched(BatchView v) {
         t0 = bcast_lane0(t0);
         if (t0 >= total) break;
         const uint64_t t1 = t0 + chunk < total ? t0 + chunk : total;
-        for (uint64_t t = t0; t < t1; ++t) run_tile<NT, F64N>(v.reqs, v.map, t, W, 0, 1, lane);
+        for (uint64_t t = t0; t < t1; ++t) run_tile<NT, F64N, RNG>(v, t, W, 0, 1, lane);
     }
 }
 
@@ -109,13 +119,13 @@ __global__ __launch_bounds__(512) void k_batched(BatchView v) {
 // tiles and of their costs (on MI355X 5% faster than giving each XCD a
 // contiguous eighth for L2 locality of the tile map, 8% on a batch that mixes
 // generators and distributions).
-template <bool NT, bool F64N>
+template <bool NT, bool F64N, bool RNG>
 __global__ __launch_bounds__(512) void k_batched_static(BatchView v) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t t = blockIdx.x;
     if (t >= v.hdr->total_tiles) return;
     const uint32_t j = wave_uniform(threadIdx.x >> 6);
-    run_tile<NT, F64N>(v.reqs, v.map, t, blockDim.x >> 6, j, 0xFFFFu, lane);
+    run_tile<NT, F64N, RNG>(v, t, blockDim.x >> 6, j, 0xFFFFu, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -151,18 +161,21 @@ static DeviceBatch *device_batch(int dev) {
     return g_devs[dev];
 }
 
-static size_t layout_bytes(uint64_t cap_req, uint64_t cap_tiles, size_t *map_off) {
-    const size_t off = sizeof(BatchHdr) + cap_req * sizeof(DevReq);
-    *map_off = off;
-    return off + cap_tiles * sizeof(uint32_t);
+// Buffer layout for a capacity: header, request rows, bounds (two words per
+// request), tile map.
+static size_t layout_bytes(uint64_t cap_req, uint64_t cap_tiles, size_t *map_off,
+                           size_t *bounds_off) {
+    *bounds_off = sizeof(BatchHdr) + cap_req * sizeof(DevReq);
+    *map_off = *bounds_off + cap_req * 2 * sizeof(uint32_t);
+    return *map_off + cap_tiles * sizeof(uint32_t);
 }
 
 static hipError_t ensure_capacity(BatchCtx &c, uint64_t nreq, uint64_t tiles) {
     if (nreq <= c.cap_req && tiles <= c.cap_tiles && c.d_buf) return hipSuccess;
     const uint64_t nr = std::max<uint64_t>(std::max<uint64_t>(nreq, c.cap_req * 3 / 2), 1024);
     const uint64_t nt = std::max<uint64_t>(std::max<uint64_t>(tiles, c.cap_tiles * 3 / 2), 65536);
-    size_t map_off;
-    const size_t bytes = layout_bytes(nr, nt, &map_off);
+    size_t map_off, bounds_off;
+    const size_t bytes = layout_bytes(nr, nt, &map_off, &bounds_off);
     hipError_t e;
     if (c.exec) { hipGraphExecDestroy(c.exec); c.exec = nullptr; }
     if (c.graph) { hipGraphDestroy(c.graph); c.graph = nullptr; }
@@ -217,28 +230,51 @@ static BatchShape batch_shape(int gen, int dist, uint64_t tiles) {
     return s;
 }
 
-template <bool F64N>
+template <bool F64N, bool RNG>
 static void *batched_kernel_v(const BatchShape &s) {
     if (s.persistent)
-        return s.nt ? reinterpret_cast<void *>(&k_batched<true, F64N>)
-                    : reinterpret_cast<void *>(&k_batched<false, F64N>);
-    return s.nt ? reinterpret_cast<void *>(&k_batched_static<true, F64N>)
-                : reinterpret_cast<void *>(&k_batched_static<false, F64N>);
+        return s.nt ? reinterpret_cast<void *>(&k_batched<true, F64N, RNG>)
+                    : reinterpret_cast<void *>(&k_batched<false, F64N, RNG>);
+    return s.nt ? reinterpret_cast<void *>(&k_batched_static<true, F64N, RNG>)
+                : reinterpret_cast<void *>(&k_batched_static<false, F64N, RNG>);
 }
 
-// The variant with the float64 normal cases only for batches that hold one.
-static void *batched_kernel(const BatchShape &s, bool f64n) {
-    return f64n ? batched_kernel_v<true>(s) : batched_kernel_v<false>(s);
+// The variants with the float64 normal cases, or with the integer-range cases,
+// only for batches that hold such a request (each set of cases raises the
+// kernel's register count, so its occupancy, for every other request).
+static void *batched_kernel(const BatchShape &s, bool f64n, bool rng) {
+    if (f64n)
+        return rng ? batched_kernel_v<true, true>(s) : batched_kernel_v<true, false>(s);
+    return rng ? batched_kernel_v<false, true>(s) : batched_kernel_v<false, false>(s);
 }
 
 int validate_request(const orng_req_t &r) {
-    if (r.gen > ORNG_PHILOX2X32 || r.dist > ORNG_F64_NORMAL || r.flags != 0) return ORNG_EINVAL;
+    if (r.gen > ORNG_PHILOX2X32 || r.dist > ORNG_I32_RANGE || r.flags != 0) return ORNG_EINVAL;
     if (!seed_ok((int)r.gen, r.seed)) return ORNG_EINVAL;
-    const uint64_t k = words_per_sample((int)r.dist), lim = sample_limit((int)r.dist);
+    if (r.dist == ORNG_I32_RANGE && r.lo >= r.hi) return ORNG_EINVAL;
+    const uint64_t lim = sample_limit((int)r.dist);
     if (r.offset > lim || r.n > lim - r.offset) return ORNG_ERANGE;
     if (r.n == 0) return ORNG_OK;
-    if (!r.out || (reinterpret_cast<uintptr_t>(r.out) & (4 * k - 1))) return ORNG_EINVAL;
+    if (!r.out || (reinterpret_cast<uintptr_t>(r.out) & (bytes_per_sample((int)r.dist) - 1)))
+        return ORNG_EINVAL;
     return ORNG_OK;
+}
+
+// Kernel-side bounds of an integer-range request: lo's bits and r = hi - lo.
+void range_bounds(const orng_req_t &r, uint32_t *lo, uint32_t *rr) {
+    const bool on = r.dist == ORNG_I32_RANGE;
+    *lo = on ? (uint32_t)r.lo : 0u;
+    *rr = on ? (uint32_t)((int64_t)r.hi - (int64_t)r.lo) : 0u;
+}
+
+// (address of out in words - first position) mod 4: the alignment class of a
+// request's output against its block grid, in words; for integer ranges,
+// whose output samples are one word each, against its sample grid.
+uint32_t output_delta(const orng_req_t &r, const void *out) {
+    const uint64_t addr_words = reinterpret_cast<uintptr_t>(out) / 4;
+    const uint64_t first =
+        r.dist == ORNG_I32_RANGE ? r.offset : r.offset * words_per_sample((int)r.dist);
+    return (uint32_t)((addr_words - first) & 3u);
 }
 
 // Tile decomposition of one request: spans of `unroll` blocks per lane,
@@ -333,9 +369,10 @@ static bool use_graphs() {
     return on;
 }
 
-// Table row of one request; `ts` is its first tile, `cnt` its tile count.
-static void make_row(DevReq &d, const orng_req_t &r, uint32_t unroll, uint64_t first_span,
-                     uint64_t ts, uint64_t cnt) {
+// Table row of one request; `ts` is its first tile, `cnt` its tile count;
+// bounds[0..1] receive its integer-range bounds.
+static void make_row(DevReq &d, uint32_t *bounds, const orng_req_t &r, uint32_t unroll,
+                     uint64_t first_span, uint64_t ts, uint64_t cnt) {
     const uint64_t kw = words_per_sample((int)r.dist);
     d.out = static_cast<char *>(r.out);
     d.p0 = r.offset * kw;  // positions and counts in stream words from here on
@@ -345,10 +382,9 @@ static void make_row(DevReq &d, const orng_req_t &r, uint32_t unroll, uint64_t f
     d.tile_start = ts;
     d.ctr = r.ctr;
     d.unroll = unroll;
-    const uint64_t addr_words = reinterpret_cast<uintptr_t>(r.out) / 4;
-    const uint32_t delta = (uint32_t)((addr_words - d.p0) & 3u);
-    d.flags = r.gen | (r.dist << 4) | (delta << 8);
+    d.flags = r.gen | (r.dist << 4) | (output_delta(r, r.out) << 8);
     d.tiles = (uint32_t)cnt;
+    range_bounds(r, &bounds[0], &bounds[1]);
 }
 
 // The (generator, distribution) pair holding most of a batch's words picks the
@@ -361,10 +397,12 @@ static int dominant_pair(const uint64_t *words) {
     return best;
 }
 
-static void unroll_table(uint32_t unroll_of[NGEN][NDIST]) {
+// Blocks per lane per tile of every (generator, request distribution); an
+// integer-range request takes its launch row from the float64 uniform one.
+static void unroll_table(uint32_t unroll_of[NGEN][NREQDIST]) {
     for (int g = 0; g < NGEN; ++g)
-        for (int d = 0; d < NDIST; ++d)
-            unroll_of[g][d] = tyche_like(g) ? 64 : tuned_fill(g, d).b_unroll;
+        for (int d = 0; d < NREQDIST; ++d)
+            unroll_of[g][d] = tyche_like(g) ? 64 : tuned_fill(g, shape_dist(d)).b_unroll;
 }
 
 int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
@@ -383,12 +421,15 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     std::vector<uint64_t> range_words(rg.T * NP, 0);
     std::vector<size_t> range_bad(rg.T, nreq);  // first invalid request of each range
     std::vector<int> range_st(rg.T, ORNG_OK);
+    std::vector<char> range_rng(rg.T, 0);       // the range holds an integer-range request
     rg.run([&](size_t t, size_t a, size_t b) {
         uint64_t *w = &range_words[t * NP];
         for (size_t i = a; i < b; ++i) {
             const int st = validate_request(reqs[i]);
             if (st != ORNG_OK) { range_bad[t] = i; range_st[t] = st; return; }
-            w[reqs[i].gen * NDIST + reqs[i].dist] += reqs[i].n * words_per_sample((int)reqs[i].dist);
+            w[reqs[i].gen * NDIST + shape_dist((int)reqs[i].dist)] +=
+                reqs[i].n * words_per_sample((int)reqs[i].dist);
+            if (reqs[i].dist == ORNG_I32_RANGE && reqs[i].n) range_rng[t] = 1;
         }
     });
     for (size_t t = 0; t < rg.T; ++t)
@@ -401,9 +442,10 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
             if (words[g * NDIST + ORNG_F64_NORMAL]) return true;
         return false;
     }();
+    const bool rng = std::find(range_rng.begin(), range_rng.end(), 1) != range_rng.end();
     const int pair = dominant_pair(words);
     const uint32_t W = batch_wg(pair / NDIST, pair % NDIST) / 64;
-    uint32_t unroll_of[NGEN][NDIST];  // one table lookup per pair, not per request
+    uint32_t unroll_of[NGEN][NREQDIST];  // one table lookup per pair, not per request
     unroll_table(unroll_of);
 
     std::unique_ptr<uint64_t[]> fspan(new uint64_t[nreq]), cnt(new uint64_t[nreq]);
@@ -438,10 +480,11 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     if (!db->capture) ORNG_TRY(hipStreamCreateWithFlags(&db->capture, hipStreamNonBlocking));
 
     const BatchShape sh = batch_shape(pair / NDIST, pair % NDIST, tiles);
-    size_t map_off;
-    layout_bytes(c.cap_req, c.cap_tiles, &map_off);
+    size_t map_off, bounds_off;
+    layout_bytes(c.cap_req, c.cap_tiles, &map_off, &bounds_off);
     BatchHdr *hdr = reinterpret_cast<BatchHdr *>(c.h_buf);
     DevReq *dq = reinterpret_cast<DevReq *>(c.h_buf + sizeof(BatchHdr));
+    uint32_t *bounds = reinterpret_cast<uint32_t *>(c.h_buf + bounds_off);
     uint32_t *map = reinterpret_cast<uint32_t *>(c.h_buf + map_off);
     std::memset(hdr, 0, sizeof(BatchHdr));
     hdr->total_tiles = tiles;
@@ -453,7 +496,8 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
         uint64_t ts = range_tiles[t];
         for (size_t i = a; i < b; ++i) {
             const orng_req_t &r = reqs[i];
-            make_row(dq[i], r, r.n ? unroll_of[r.gen][r.dist] : 0, fspan[i], ts, cnt[i]);
+            make_row(dq[i], bounds + 2 * i, r, r.n ? unroll_of[r.gen][r.dist] : 0, fspan[i], ts,
+                     cnt[i]);
             std::fill_n(map + ts, cnt[i], (uint32_t)i);
             ts += cnt[i];
         }
@@ -462,21 +506,25 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
                             hipMemcpyHostToDevice, stream));
     ORNG_TRY(hipMemcpyAsync(c.d_buf + map_off, c.h_buf + map_off, tiles * sizeof(uint32_t),
                             hipMemcpyHostToDevice, stream));
+    if (rng)
+        ORNG_TRY(hipMemcpyAsync(c.d_buf + bounds_off, c.h_buf + bounds_off,
+                                nreq * 2 * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
 
     BatchView v;
     v.hdr = reinterpret_cast<BatchHdr *>(c.d_buf);
     v.reqs = reinterpret_cast<const DevReq *>(c.d_buf + sizeof(BatchHdr));
     v.map = reinterpret_cast<const uint32_t *>(c.d_buf + map_off);
+    v.bounds = reinterpret_cast<const uint32_t *>(c.d_buf + bounds_off);
     void *args[] = {&v};
     if (use_graphs()) {
         const uint64_t key[4] = {reinterpret_cast<uintptr_t>(c.d_buf), sh.wg, sh.grid,
                                  (uint64_t)sh.nt | ((uint64_t)sh.persistent << 1) |
-                                     ((uint64_t)f64n << 2)};
+                                     ((uint64_t)f64n << 2) | ((uint64_t)rng << 3)};
         if (!c.exec || std::memcmp(key, c.graph_key, sizeof key) != 0) {
             if (c.exec) { hipGraphExecDestroy(c.exec); c.exec = nullptr; }
             if (c.graph) { hipGraphDestroy(c.graph); c.graph = nullptr; }
             ORNG_TRY(hipStreamBeginCapture(db->capture, hipStreamCaptureModeThreadLocal));
-            hipError_t le = hipLaunchKernel(batched_kernel(sh, f64n), dim3(sh.grid),
+            hipError_t le = hipLaunchKernel(batched_kernel(sh, f64n, rng), dim3(sh.grid),
                                             dim3(sh.wg), args, 0, db->capture);
             hipError_t ce = hipStreamEndCapture(db->capture, &c.graph);
             ORNG_TRY(le);
@@ -486,8 +534,8 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
         }
         ORNG_TRY(hipGraphLaunch(c.exec, stream));
     } else {
-        ORNG_TRY(hipLaunchKernel(batched_kernel(sh, f64n), dim3(sh.grid), dim3(sh.wg), args, 0,
-                                 stream));
+        ORNG_TRY(hipLaunchKernel(batched_kernel(sh, f64n, rng), dim3(sh.grid), dim3(sh.wg), args,
+                                 0, stream));
     }
     ORNG_TRY(hipEventRecord(c.done, stream));
 #undef ORNG_TRY
@@ -512,14 +560,17 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
 // other in stream order; calls that overlap on one device race.
 constexpr uint64_t NOALLOC_ROWS_END =
     sizeof(BatchHdr) + (uint64_t)ORNG_NOALLOC_MAX_REQUESTS * sizeof(DevReq);
-constexpr uint64_t NOALLOC_MAP_OFF = (NOALLOC_ROWS_END + 255) / 256 * 256;
+constexpr uint64_t NOALLOC_BOUNDS_OFF = NOALLOC_ROWS_END;  // two words per request
+constexpr uint64_t NOALLOC_STAGE_END =
+    NOALLOC_BOUNDS_OFF + (uint64_t)ORNG_NOALLOC_MAX_REQUESTS * 2 * sizeof(uint32_t);
+constexpr uint64_t NOALLOC_MAP_OFF = (NOALLOC_STAGE_END + 255) / 256 * 256;
 constexpr uint64_t NOALLOC_BYTES =
     NOALLOC_MAP_OFF + (uint64_t)ORNG_NOALLOC_MAX_TILES * sizeof(uint32_t);
 
 static __device__ __align__(256) char scratch[NOALLOC_BYTES];
 
 static std::mutex g_na_mu;                        // one allocation-free call at a time per process
-alignas(64) static char g_na_stage[NOALLOC_ROWS_END];  // host: header + request rows
+alignas(64) static char g_na_stage[NOALLOC_STAGE_END];  // host: header, rows, bounds
 constexpr int NOALLOC_MAX_DEVICES = 64;
 static char *g_na_ptr[NOALLOC_MAX_DEVICES];       // device address of `scratch`, per device
 
@@ -538,28 +589,32 @@ int fill_batched_noalloc(const orng_req_t *reqs, size_t nreq, hipStream_t stream
     if (!nreq) return ORNG_OK;
     constexpr int NP = NGEN * NDIST;
     uint64_t words[NP] = {0};
+    bool rng = false;
     for (size_t i = 0; i < nreq; ++i) {
         const int st = validate_request(reqs[i]);
         if (st != ORNG_OK) return st;
-        words[reqs[i].gen * NDIST + reqs[i].dist] += reqs[i].n * words_per_sample((int)reqs[i].dist);
+        words[reqs[i].gen * NDIST + shape_dist((int)reqs[i].dist)] +=
+            reqs[i].n * words_per_sample((int)reqs[i].dist);
+        rng = rng || (reqs[i].dist == ORNG_I32_RANGE && reqs[i].n);
     }
     if (nreq > ORNG_NOALLOC_MAX_REQUESTS) return ORNG_ENOMEM;
     bool f64n = false;
     for (int g = 0; g < NGEN; ++g) f64n = f64n || words[g * NDIST + ORNG_F64_NORMAL] != 0;
     const int pair = dominant_pair(words);
     const uint32_t W = batch_wg(pair / NDIST, pair % NDIST) / 64;
-    uint32_t unroll_of[NGEN][NDIST];
+    uint32_t unroll_of[NGEN][NREQDIST];
     unroll_table(unroll_of);
 
     std::lock_guard<std::mutex> lk(g_na_mu);
     DevReq *rows = reinterpret_cast<DevReq *>(g_na_stage + sizeof(BatchHdr));
+    uint32_t *bounds = reinterpret_cast<uint32_t *>(g_na_stage + NOALLOC_BOUNDS_OFF);
     uint64_t tiles = 0;
     for (size_t i = 0; i < nreq; ++i) {
         const orng_req_t &r = reqs[i];
         uint64_t fs = 0, cnt = 0;
         if (r.n) request_tiles(r, unroll_of[r.gen][r.dist], W, &fs, &cnt);
         if (cnt > ORNG_NOALLOC_MAX_TILES - tiles) return ORNG_ENOMEM;
-        make_row(rows[i], r, r.n ? unroll_of[r.gen][r.dist] : 0, fs, tiles, cnt);
+        make_row(rows[i], bounds + 2 * i, r, r.n ? unroll_of[r.gen][r.dist] : 0, fs, tiles, cnt);
         tiles += cnt;
     }
     if (tiles == 0) return ORNG_OK;
@@ -587,17 +642,21 @@ int fill_batched_noalloc(const orng_req_t *reqs, size_t nreq, hipStream_t stream
 #define ORNG_TRY(x) do { e = (x); if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; } } while (0)
     ORNG_TRY(hipMemcpyAsync(base, g_na_stage, sizeof(BatchHdr) + nreq * sizeof(DevReq),
                             hipMemcpyHostToDevice, stream));
+    if (rng)
+        ORNG_TRY(hipMemcpyAsync(base + NOALLOC_BOUNDS_OFF, g_na_stage + NOALLOC_BOUNDS_OFF,
+                                nreq * 2 * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
     BatchView v;
     v.hdr = reinterpret_cast<BatchHdr *>(base);
     v.reqs = reinterpret_cast<const DevReq *>(base + sizeof(BatchHdr));
     v.map = reinterpret_cast<const uint32_t *>(base + NOALLOC_MAP_OFF);
+    v.bounds = reinterpret_cast<const uint32_t *>(base + NOALLOC_BOUNDS_OFF);
     uint32_t *map = reinterpret_cast<uint32_t *>(base + NOALLOC_MAP_OFF);
     const uint32_t nr = (uint32_t)nreq;
     void *margs[] = {&v.reqs, const_cast<uint32_t *>(&nr), &map};
     ORNG_TRY(hipLaunchKernel(reinterpret_cast<void *>(&k_tile_map), dim3((nr + 3) / 4), dim3(256),
                              margs, 0, stream));
     void *args[] = {&v};
-    ORNG_TRY(hipLaunchKernel(batched_kernel(sh, f64n), dim3(sh.grid), dim3(sh.wg), args, 0,
+    ORNG_TRY(hipLaunchKernel(batched_kernel(sh, f64n, rng), dim3(sh.grid), dim3(sh.wg), args, 0,
                              stream));
 #undef ORNG_TRY
     return ORNG_OK;
@@ -624,6 +683,12 @@ int orng_fill_each(const orng_req_t *h_reqs, size_t nreq, void *stream) {
     for (size_t i = 0; i < nreq; ++i) {
         const orng_req_t &r = h_reqs[i];
         if (!r.n) continue;
+        if (r.dist == ORNG_I32_RANGE) {
+            const int st = orng_fill_range((int)r.gen, r.seed, r.ctr, 1, r.offset, r.n, r.lo,
+                                           r.hi, static_cast<int32_t *>(r.out), stream);
+            if (st != ORNG_OK) return st;
+            continue;
+        }
         const uint64_t k = orng::words_per_sample((int)r.dist);
         hipError_t e = orng::launch_fill((int)r.gen, (int)r.dist, r.seed, r.ctr, 1, r.offset * k,
                                          r.n * k, r.out, static_cast<hipStream_t>(stream));

@@ -25,8 +25,12 @@ namespace orng {
 enum GenId : int { G_PHILOX = 0, G_TF4X32 = 1, G_TF2X64 = 2, G_SQUARES = 3, G_TYCHE = 4,
                    G_TF4X32_13 = 5, G_TF2X64_13 = 6, G_TYCHE_I = 7, G_SQUARES64 = 8,
                    G_PHILOX2X32 = 9 };
-enum DistId : int { D_U32 = 0, D_UNIFORM = 1, D_NORMAL = 2, D_F64U = 3, D_F64N = 4 };
-constexpr int NGEN = 10, NDIST = 5;
+enum DistId : int { D_U32 = 0, D_UNIFORM = 1, D_NORMAL = 2, D_F64U = 3, D_F64N = 4,
+                    D_I32R = 5 };
+// NDIST: distributions of the fill kernels and launch tables; request records
+// (batched and served) also take D_I32R, integers in [lo, hi), whose bounds
+// they carry.
+constexpr int NGEN = 10, NDIST = 5, NREQDIST = 6;
 
 // Tyche and Tyche-i share the tile layout (no random access within a
 // substream); every other generator is counter-based with 4-word blocks.
@@ -610,6 +614,20 @@ __device__ __forceinline__ void convert4(uint32_t w[4]) {
         w[0] = (uint32_t)__double2loint(a); w[1] = (uint32_t)__double2hiint(a);
         w[2] = (uint32_t)__double2loint(b); w[3] = (uint32_t)__double2hiint(b);
     }
+}
+
+// Integer sample in [lo, hi) from the word pair (w0, w1) of its two stream
+// positions: lo + floor(((w1 << 32) | w0) r / 2^64), r = hi - lo < 2^32.  With
+// x = w1 2^32 + w0, floor(x r / 2^64) = floor((w1 r + floor(w0 r / 2^32)) / 2^32):
+// the high half of w0 r, then w1 r plus a 64-bit addend whose low word is that
+// half and whose high word is lo -- adding lo 2^32 to the sum adds lo to its
+// high word (a carry out of bit 63 is dropped, as a 32-bit add of lo drops
+// it).  lo is passed as its two's-complement bits.
+__device__ __forceinline__ uint32_t range_sample(uint32_t w0, uint32_t w1, uint32_t r,
+                                                 uint32_t lo) {
+    const uint32_t t = __umulhi(w0, r);
+    const uint64_t s = (uint64_t)w1 * r + (((uint64_t)lo << 32) | t);
+    return (uint32_t)(s >> 32);
 }
 
 // Words of counter block `blk` (positions 4*blk .. 4*blk+3) of stream ctr.

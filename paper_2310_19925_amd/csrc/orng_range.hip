@@ -8,7 +8,8 @@
 // two 32x32->64 multiply-adds, and the sum stays below 2^64.  Each value has
 // floor(2^64 / r) or ceil(2^64 / r) preimages, so its probability is within
 // 2^-64 of 1/r; no remainder is taken and no sample is rejected, so every
-// sample keeps its fixed pair of stream positions.
+// sample keeps its fixed pair of stream positions.  (range_sample, in the
+// device header, is shared with the batched and served kernels.)
 //
 // Work decomposition.  A wave handles one group per loop trip.  Counter
 // generators: a group is 256 samples; lane l makes blocks 2m and 2m+1,
@@ -26,22 +27,12 @@
 #include "../../include/orng.h"
 #include "orng_device.hpp"
 #include "orng_internal.hpp"
+#include "orng_span.hpp"
 
 namespace orng {
 
 constexpr uint64_t RANGE_GROUP = 256;                       // samples, counter generators
 constexpr uint64_t RANGE_TILE = TYCHE_TILE_WORDS / 2;       // samples per Tyche tile
-
-// lo + floor(((w1 << 32) | w0) r / 2^64) (mod 2^32) in two instructions: the
-// high half of w0 r, then w1 r plus a 64-bit addend whose low word is that
-// half and whose high word is lo -- adding lo 2^32 to the sum adds lo to its
-// high word (a carry out of bit 63 is dropped, as a 32-bit add of lo drops it).
-__device__ __forceinline__ uint32_t range_sample(uint32_t w0, uint32_t w1, uint32_t r,
-                                                 uint32_t lo) {
-    const uint32_t t = __umulhi(w0, r);
-    const uint64_t s = (uint64_t)w1 * r + (((uint64_t)lo << 32) | t);
-    return (uint32_t)(s >> 32);
-}
 
 struct RangeArgs {
     KeySched ks;
@@ -55,24 +46,6 @@ struct RangeArgs {
     uint32_t mis;               // (stream 0 output address in words - s0) mod 4
     uint32_t unroll;            // groups per span (counter generators)
 };
-
-template <int N>
-__device__ __forceinline__ void range_store(int32_t *base, uint64_t q, uint64_t s0, uint64_t send,
-                                            bool aligned, const uint32_t v[N]) {
-    if (aligned && q >= s0 && q + N <= send) {
-        if constexpr (N == 4) {
-            typedef uint32_t u4 __attribute__((ext_vector_type(4)));
-            *reinterpret_cast<u4 *>(base + (q - s0)) = u4{v[0], v[1], v[2], v[3]};
-        } else {
-            typedef uint32_t u2 __attribute__((ext_vector_type(2)));
-            *reinterpret_cast<u2 *>(base + (q - s0)) = u2{v[0], v[1]};
-        }
-        return;
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-        if (q + i >= s0 && q + i < send) base[q + i - s0] = (int32_t)v[i];
-}
 
 // Group g of a counter generator's stream: lane l makes blocks 2m and 2m + 1,
 // m = 64 g + l, i.e. samples 4m .. 4m + 3, and writes them with one 16-byte
@@ -90,7 +63,7 @@ __device__ __forceinline__ void range_group(const RangeArgs &a, uint64_t g, uint
                            range_sample(w[2], w[3], a.r, a.lo),
                            range_sample(x[0], x[1], a.r, a.lo),
                            range_sample(x[2], x[3], a.r, a.lo)};
-    range_store<4>(base, 4 * m, a.s0, send, aligned, v);
+    store_samples<4, false>(base, 4 * m, a.s0, send, aligned, v);
 }
 
 // One span per wave and loop trip, like the fill kernels: counter generators
@@ -128,7 +101,7 @@ __global__ __launch_bounds__(512) void k_range(RangeArgs a) {
                 if (2 * (bw + 64) <= a.s0) continue;
                 const uint32_t v[2] = {range_sample(w[0], w[1], a.r, a.lo),
                                        range_sample(w[2], w[3], a.r, a.lo)};
-                range_store<2>(base, 2 * (bw + lane), a.s0, send, (mis & 1u) == 0, v);
+                store_samples<2, false>(base, 2 * (bw + lane), a.s0, send, (mis & 1u) == 0, v);
             }
         } else {
             const uint64_t g0 = span * a.unroll;
@@ -206,7 +179,7 @@ __global__ __launch_bounds__(256) void k_range_units(RangeUnitArgs a) {
         st.next4(w);
         const uint32_t v[2] = {range_sample(w[0], w[1], a.r, a.lo),
                                range_sample(w[2], w[3], a.r, a.lo)};
-        range_store<2>(base, 2 * (uint64_t)u, a.s0, send, false, v);
+        store_samples<2, false>(base, 2 * (uint64_t)u, a.s0, send, false, v);
     } else {
         uint32_t w[4], x[4];
         counter_block<G>(2 * u, ctr, a.ks, w);
@@ -215,7 +188,7 @@ __global__ __launch_bounds__(256) void k_range_units(RangeUnitArgs a) {
                                range_sample(w[2], w[3], a.r, a.lo),
                                range_sample(x[0], x[1], a.r, a.lo),
                                range_sample(x[2], x[3], a.r, a.lo)};
-        range_store<4>(base, 4 * (uint64_t)u, a.s0, send, false, v);
+        store_samples<4, false>(base, 4 * (uint64_t)u, a.s0, send, false, v);
     }
 }
 

@@ -182,26 +182,125 @@ __device__ __forceinline__ void process_span(const KeySched &ks, uint32_t ctr, c
     }
 }
 
+// Store the N (2 or 4) int32 samples whose first sample number is q into
+// base[q - s0], q in [s0, send): one 8- or 16-byte store when the whole group
+// is in range and `aligned` (the address of sample q is a multiple of 4 N
+// bytes), else one masked word at a time.
+template <int N, bool NT>
+__device__ __forceinline__ void store_samples(int32_t *base, uint64_t q, uint64_t s0,
+                                              uint64_t send, bool aligned, const uint32_t v[N]) {
+    static_assert(N == 2 || N == 4, "sample group");
+    if (aligned && q >= s0 && q + N <= send) {
+        if constexpr (N == 4) {
+            store16<NT>(reinterpret_cast<char *>(base + (q - s0)), v);
+        } else {
+            typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+            u32x2 x = {v[0], v[1]};
+            u32x2 *p = reinterpret_cast<u32x2 *>(base + (q - s0));
+            if constexpr (NT)
+                __builtin_nontemporal_store(x, p);
+            else
+                *p = x;
+        }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (q + i >= s0 && q + i < send) base[q + i - s0] = (int32_t)v[i];
+}
+
+// A span of integer samples in [lo, hi) (D_I32R), in the span numbering of
+// process_span: block b of the stream gives samples 2b and 2b + 1 (its word
+// pairs), so p0 and pend, in words, are twice the first and end sample.
+// Counter generators: where two iterations of the span remain, lane l makes
+// the adjacent blocks bw + 2l and bw + 2l + 1 of the 128-block window, so its
+// four samples are one 16-byte store and the wave writes 1 KiB per store
+// instruction; a last single iteration makes block bw + l (one 8-byte store).
+// Tyche: block k*64 + l of the tile from lane l's substream, one 8-byte store.
+// mis = (output address in words - first sample) mod 4 decides which
+// stores are aligned; samples outside the range are never written.
+template <int G, bool NT>
+__device__ __forceinline__ void process_span_range(const KeySched &ks, uint32_t ctr,
+                                                   int32_t *base, uint64_t p0, uint64_t pend,
+                                                   uint64_t span, uint32_t unroll,
+                                                   uint32_t mis, uint32_t lane, uint32_t lo,
+                                                   uint32_t r) {
+    const uint64_t s0 = p0 / 2, send = pend / 2;
+    const bool al2 = (mis & 1u) == 0, al4 = mis == 0;
+    if constexpr (tyche_like(G)) {
+        TycheT<G == G_TYCHE_I> st;
+        st.seed(ks, (uint32_t)span * 64u + lane, ctr);
+        const uint64_t tile_block = span * TYCHE_TILE_BLOCKS;
+        for (uint32_t k = 0; k < 64; ++k) {
+            const uint64_t bw = tile_block + 64u * k;
+            if (2 * bw >= send) break;
+            uint32_t w[4];
+            st.next4(w);
+            if (2 * (bw + 64) <= s0) continue;
+            const uint32_t v[2] = {range_sample(w[0], w[1], r, lo), range_sample(w[2], w[3], r, lo)};
+            store_samples<2, NT>(base, 2 * (bw + lane), s0, send, al2, v);
+        }
+    } else {
+        const uint64_t b0 = span * 64u * unroll;
+        for (uint32_t u = 0; u < unroll;) {
+            const uint64_t bw = b0 + 64u * u;
+            if (2 * bw >= send) break;
+            if (u + 1 < unroll) {
+                if (2 * (bw + 128) > s0) {
+                    const uint64_t b = bw + 2u * lane;
+                    uint32_t w[4], x[4];
+                    counter_block<G>((uint32_t)b, ctr, ks, w);
+                    counter_block<G>((uint32_t)(b + 1), ctr, ks, x);
+                    const uint32_t v[4] = {range_sample(w[0], w[1], r, lo),
+                                           range_sample(w[2], w[3], r, lo),
+                                           range_sample(x[0], x[1], r, lo),
+                                           range_sample(x[2], x[3], r, lo)};
+                    store_samples<4, NT>(base, 2 * b, s0, send, al4, v);
+                }
+                u += 2;
+                continue;
+            }
+            if (2 * (bw + 64) > s0) {
+                const uint64_t b = bw + lane;
+                uint32_t w[4];
+                counter_block<G>((uint32_t)b, ctr, ks, w);
+                const uint32_t v[2] = {range_sample(w[0], w[1], r, lo),
+                                       range_sample(w[2], w[3], r, lo)};
+                store_samples<2, NT>(base, 2 * b, s0, send, al2, v);
+            }
+            ++u;
+        }
+    }
+}
+
 // Workgroups are dealt to the 8 XCDs of the device round-robin (workgroup b
 // runs on XCD b mod 8); the batched and served launchers round their grids to
 // a multiple of this.
 constexpr uint32_t XCDS = 8;
 
 // Runtime (gen, dist) dispatch for kernels whose requests mix generators.
-// F64N selects whether the float64 normal cases are compiled in: their code
-// needs more than twice the vector registers of every other case, and a
-// kernel's register count (so its occupancy) is that of its largest case, so
-// the launchers use the variant without them unless a request needs them.
-template <bool NT, bool F64N>
+// F64N and RNG select whether the float64 normal and the integer-range cases
+// are compiled in: the float64 normal code needs more than twice the vector
+// registers of every other case, the range cases raise the persistent batched
+// kernel's count too, and a kernel's register count (so its occupancy) is that
+// of its largest case, so the launchers use a variant without them unless a
+// request needs them.  lo and r (= hi - lo) are read by the range cases only.
+template <bool NT, bool F64N, bool RNG>
 __device__ __forceinline__ void process_span_any(int gen, int dist, const KeySched &ks,
                                                  uint32_t ctr, char *base, uint64_t p0,
                                                  uint64_t pend, uint64_t span, uint32_t unroll,
-                                                 uint32_t delta, uint32_t lane) {
+                                                 uint32_t delta, uint32_t lane, uint32_t lo,
+                                                 uint32_t r) {
 #define ORNG_CASE(G, D)                                                                    \
-    case G * NDIST + D:                                                                    \
+    case G * 8 + D:                                                                        \
         process_span<G, D, NT>(ks, ctr, base, p0, pend, span, unroll, delta, lane);        \
         break;
-    switch (gen * NDIST + dist) {
+#define ORNG_RCASE(G)                                                                      \
+    case G * 8 + D_I32R:                                                                   \
+        process_span_range<G, NT>(ks, ctr, reinterpret_cast<int32_t *>(base), p0, pend,    \
+                                  span, unroll, delta, lane, lo, r);                       \
+        break;
+    switch (gen * 8 + dist) {
         ORNG_CASE(0, 0) ORNG_CASE(0, 1) ORNG_CASE(0, 2) ORNG_CASE(0, 3)
         ORNG_CASE(1, 0) ORNG_CASE(1, 1) ORNG_CASE(1, 2) ORNG_CASE(1, 3)
         ORNG_CASE(2, 0) ORNG_CASE(2, 1) ORNG_CASE(2, 2) ORNG_CASE(2, 3)
@@ -214,16 +313,24 @@ __device__ __forceinline__ void process_span_any(int gen, int dist, const KeySch
         ORNG_CASE(9, 0) ORNG_CASE(9, 1) ORNG_CASE(9, 2) ORNG_CASE(9, 3)
         default:
             if constexpr (F64N) {
-                switch (gen * NDIST + dist) {
+                switch (gen * 8 + dist) {
                     ORNG_CASE(0, 4) ORNG_CASE(1, 4) ORNG_CASE(2, 4) ORNG_CASE(3, 4)
                     ORNG_CASE(4, 4) ORNG_CASE(5, 4) ORNG_CASE(6, 4) ORNG_CASE(7, 4)
                     ORNG_CASE(8, 4) ORNG_CASE(9, 4)
                     default: break;
                 }
             }
+            if constexpr (RNG) {
+                switch (gen * 8 + dist) {
+                    ORNG_RCASE(0) ORNG_RCASE(1) ORNG_RCASE(2) ORNG_RCASE(3) ORNG_RCASE(4)
+                    ORNG_RCASE(5) ORNG_RCASE(6) ORNG_RCASE(7) ORNG_RCASE(8) ORNG_RCASE(9)
+                    default: break;
+                }
+            }
             break;
     }
 #undef ORNG_CASE
+#undef ORNG_RCASE
 }
 
 // Blocks per span for a generator.

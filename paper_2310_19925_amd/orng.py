@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "liborng.so")
 PHILOX4X32_10, THREEFRY4X32_20, THREEFRY2X64_20, SQUARES32, TYCHE = range(5)
 THREEFRY4X32_13, THREEFRY2X64_13, TYCHE_I, SQUARES64, PHILOX2X32 = 5, 6, 7, 8, 9
 U32, F32_UNIFORM, F32_NORMAL, F64_UNIFORM, F64_NORMAL = range(5)
+I32_RANGE = 5  # request records only (batched, served): integers in [lo, hi)
 OK, EINVAL, ERANGE, ENOMEM, EAGAIN, EBUSY, EHIP, ENOENT = 0, -1, -2, -3, -4, -5, -6, -7
 TUNE_RANGE = 5  # orng_autotune(gen, TUNE_RANGE): the integer-range fill
 
@@ -59,7 +60,8 @@ class orng_serve_stats_t(C.Structure):
 class orng_req_t(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("offset", C.c_uint64), ("n", C.c_uint64),
                 ("out", C.c_void_p), ("ctr", C.c_uint32), ("gen", C.c_uint32),
-                ("dist", C.c_uint32), ("flags", C.c_uint32)]
+                ("dist", C.c_uint32), ("flags", C.c_uint32), ("lo", C.c_int32),
+                ("hi", C.c_int32)]
 
 
 def _load():
@@ -187,31 +189,36 @@ def orng_normal_pairs(x0, x1, n, z0, z1, stream=None):
            "orng_normal_pairs")
 
 
-# orng_req_t as a numpy structured dtype (48 bytes, same field order)
+# orng_req_t as a numpy structured dtype (56 bytes, same field order)
+REQ_BYTES = 56
+
+
 def _req_dtype():
     import numpy as np
     return np.dtype([("seed", "<u8"), ("offset", "<u8"), ("n", "<u8"), ("out", "<u8"),
-                     ("ctr", "<u4"), ("gen", "<u4"), ("dist", "<u4"), ("flags", "<u4")],
-                    align=False)
+                     ("ctr", "<u4"), ("gen", "<u4"), ("dist", "<u4"), ("flags", "<u4"),
+                     ("lo", "<i4"), ("hi", "<i4")], align=False)
 
 
-def make_requests(gen, dist, seed, ctr, offset, n, out_ptr):
+def make_requests(gen, dist, seed, ctr, offset, n, out_ptr, lo=0, hi=0):
     """Build a contiguous orng_req_t array from per-request sequences (or
-    scalars broadcast to the common length).  out_ptr: device addresses."""
+    scalars broadcast to the common length).  out_ptr: device addresses;
+    lo, hi: bounds of I32_RANGE requests (ignored for the others)."""
     import numpy as np
-    cols = [np.asarray(x) for x in (gen, dist, seed, ctr, offset, n, out_ptr)]
+    cols = [np.asarray(x) for x in (gen, dist, seed, ctr, offset, n, out_ptr, lo, hi)]
     m = max(c.size for c in cols)
     r = np.zeros(m, dtype=_req_dtype())
     r["gen"], r["dist"] = cols[0], cols[1]
     r["seed"], r["ctr"] = cols[2].astype(np.uint64), cols[3].astype(np.uint32)
     r["offset"], r["n"] = cols[4].astype(np.uint64), cols[5].astype(np.uint64)
     r["out"] = cols[6].astype(np.uint64)
+    r["lo"], r["hi"] = cols[7].astype(np.int32), cols[8].astype(np.int32)
     return r
 
 
 def orng_fill_batched(reqs, stream=None):
     """reqs: numpy array of dtype _req_dtype() (see make_requests)."""
-    assert reqs.dtype.itemsize == 48 and reqs.flags["C_CONTIGUOUS"]
+    assert reqs.dtype.itemsize == REQ_BYTES and reqs.flags["C_CONTIGUOUS"]
     _check(_lib.orng_fill_batched(reqs.ctypes.data if reqs.size else None, reqs.size,
                                   _stream(stream)), "orng_fill_batched")
 
@@ -219,7 +226,7 @@ def orng_fill_batched(reqs, stream=None):
 def orng_fill_batched_noalloc(reqs, stream=None):
     """As orng_fill_batched, with the batch tables in the library's fixed
     device array (no allocation; see include/orng.h for the limits)."""
-    assert reqs.dtype.itemsize == 48 and reqs.flags["C_CONTIGUOUS"]
+    assert reqs.dtype.itemsize == REQ_BYTES and reqs.flags["C_CONTIGUOUS"]
     _check(_lib.orng_fill_batched_noalloc(reqs.ctypes.data if reqs.size else None, reqs.size,
                                           _stream(stream)), "orng_fill_batched_noalloc")
 
@@ -228,7 +235,7 @@ NOALLOC_MAX_REQUESTS, NOALLOC_MAX_TILES = 131072, 4194304
 
 
 def orng_fill_each(reqs, stream=None):
-    assert reqs.dtype.itemsize == 48 and reqs.flags["C_CONTIGUOUS"]
+    assert reqs.dtype.itemsize == REQ_BYTES and reqs.flags["C_CONTIGUOUS"]
     _check(_lib.orng_fill_each(reqs.ctypes.data if reqs.size else None, reqs.size,
                                _stream(stream)), "orng_fill_each")
 
@@ -249,17 +256,17 @@ def orng_serve_create(arena_bytes, arena=None, max_slots=0, step_words=0):
     return h.value
 
 
-def orng_serve_submit(srv, gen, dist, seed, ctr, offset, n, out=None):
-    r = orng_req_t(seed, offset, n, _ptr(out), ctr, gen, dist, 0)
+def orng_serve_submit(srv, gen, dist, seed, ctr, offset, n, out=None, lo=0, hi=0):
+    r = orng_req_t(seed, offset, n, _ptr(out), ctr, gen, dist, 0, lo, hi)
     t = C.c_uint64()
     _check(_lib.orng_serve_submit(srv, C.byref(r), C.byref(t)), "orng_serve_submit")
     return t.value
 
 
-def orng_serve_try_submit(srv, gen, dist, seed, ctr, offset, n, out=None):
+def orng_serve_try_submit(srv, gen, dist, seed, ctr, offset, n, out=None, lo=0, hi=0):
     """Non-blocking submit: the ticket, or None when the server cannot admit
     the request at once (ORNG_EAGAIN; nothing was queued)."""
-    r = orng_req_t(seed, offset, n, _ptr(out), ctr, gen, dist, 0)
+    r = orng_req_t(seed, offset, n, _ptr(out), ctr, gen, dist, 0, lo, hi)
     t = C.c_uint64()
     st = _lib.orng_serve_try_submit(srv, C.byref(r), C.byref(t))
     if st == EAGAIN:
@@ -272,7 +279,7 @@ def orng_serve_submit_many(srv, reqs):
     """reqs: numpy array of orng_req_t records (make_requests; out = 0 asks for
     an arena output).  Returns a numpy array of tickets."""
     import numpy as np
-    assert reqs.dtype.itemsize == 48 and reqs.flags["C_CONTIGUOUS"]
+    assert reqs.dtype.itemsize == REQ_BYTES and reqs.flags["C_CONTIGUOUS"]
     t = np.zeros(reqs.size, dtype=np.uint64)
     _check(_lib.orng_serve_submit_many(srv, reqs.ctypes.data if reqs.size else None, reqs.size,
                                        t.ctypes.data if reqs.size else None),
@@ -333,8 +340,8 @@ def orng_serve_destroy(srv):
 # -------- convenience wrappers that allocate the output tensor ---------------
 def _torch_dtype(dist):
     import torch
-    return {U32: torch.int32, F64_UNIFORM: torch.float64, F64_NORMAL: torch.float64}.get(
-        dist, torch.float32)
+    return {U32: torch.int32, F64_UNIFORM: torch.float64, F64_NORMAL: torch.float64,
+            I32_RANGE: torch.int32}.get(dist, torch.float32)
 
 
 def fill(gen, dist, seed, ctr, offset, n, device="cuda", stream=None):

@@ -70,7 +70,7 @@ def test_header_is_plain_c_and_links(tmp_path):
         '  if (orng_get_launch(&l) != ORNG_OK) return 1;\n'
         '  if (orng_fill(ORNG_SQUARES64 + 1, ORNG_U32, 1, 1, 0, 4, (void*)0, (void*)0) != ORNG_EINVAL) return 2;\n'
         '  printf("%s %d\\n", orng_strerror(ORNG_ERANGE), orng_version());\n'
-        '  return sizeof(orng_req_t) == 48 ? 0 : 3;\n'
+        '  return sizeof(orng_req_t) == 56 ? 0 : 3;\n'
         '}\n')
     exe = tmp_path / "t"
     libdir = os.path.dirname(LIB)
@@ -92,7 +92,9 @@ def test_noalloc_batched_limits_without_gpu():
     fn.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     fn.restype = ctypes.c_int
     dt = np.dtype([("seed", "<u8"), ("offset", "<u8"), ("n", "<u8"), ("out", "<u8"),
-                   ("ctr", "<u4"), ("gen", "<u4"), ("dist", "<u4"), ("flags", "<u4")])
+                   ("ctr", "<u4"), ("gen", "<u4"), ("dist", "<u4"), ("flags", "<u4"),
+                   ("lo", "<i4"), ("hi", "<i4")])
+    assert dt.itemsize == 56  # sizeof(orng_req_t)
     max_req, max_tiles = 131072, 4194304
     hdr = open(os.path.join(ROOT, "include", "orng.h")).read()
     assert "ORNG_NOALLOC_MAX_REQUESTS = %d" % max_req in hdr

@@ -204,3 +204,107 @@ def test_autotune_writes_cache_and_keeps_results(R, O, tmp_path):
     out = R.fill(0, 3, 9, 9, 3, 100003)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.int64), O.fill(0, 3, 9, 9, 3, 100003).view(np.int64))
+
+
+def _range_mix(rng, m, max_log2=14):
+    """A batch mixing integer-range requests (every generator, bounds from one
+    value to the whole int32 span, offsets near both ends of the 2^31 samples
+    of a stream) with 32-bit fills.  Returns the request columns and lo, hi."""
+    gen, dist, seed, ctr, off, L = _random_batch(rng, m, max_log2, dists=[0, 1, 2, 5, 5, 5])
+    isr = dist == 5
+    lim = 2**31
+    roff = np.floor(rng.random(m) * (lim - L + 1)).astype(np.uint64)
+    roff[: m // 10] = rng.integers(0, 64, m // 10)
+    roff[m // 10: m // 5] = lim - L[m // 10: m // 5]
+    off = np.where(isr, roff, off)
+    kinds = rng.integers(0, 5, m)
+    lo = rng.integers(-2**31, 2**31 - 1, m, dtype=np.int64)          # at most 2^31 - 2
+    r = np.exp(rng.random(m) * np.log(2.0**32 - 1)).astype(np.int64)  # 1 .. 2^32 - 1
+    r = np.where(kinds == 1, 1, r)                                    # a single value
+    r = np.where(kinds == 2, 6, r)                                    # a die
+    r = np.where(kinds == 3, 2 ** rng.integers(1, 32, m), r)          # powers of two
+    hi = np.minimum(lo + np.maximum(r, 1), 2**31 - 1)
+    lo = np.where(kinds == 0, -2**31, lo)                             # the whole int32 span
+    hi = np.where(kinds == 0, 2**31 - 1, hi)
+    assert np.all((lo >= -2**31) & (hi <= 2**31 - 1) & (lo < hi))
+    return gen, dist, seed, ctr, off, L, lo.astype(np.int32), hi.astype(np.int32)
+
+
+def _check_range_mix(R, O, batch, call, pad=1):
+    gen, dist, seed, ctr, off, L, lo, hi = batch
+    m = len(L)
+    starts = np.zeros(m + 1, np.int64)
+    np.cumsum(L + 1, out=starts[1:])  # one guard word between requests: mixed alignment
+    buf = torch.full((int(starts[-1]) + pad + 1,), -1, dtype=torch.int32, device="cuda")
+    base = buf.data_ptr() + 4 * pad
+    reqs = R.make_requests(gen, dist, seed, ctr, off, L, base + 4 * starts[:-1], lo, hi)
+    call(reqs)
+    torch.cuda.synchronize()
+    host = buf.cpu().numpy().view(np.uint32)[pad:]
+    for i in range(m):
+        got = host[starts[i]:starts[i] + L[i]]
+        if dist[i] == R.I32_RANGE:
+            ref = O.fill_range(int(gen[i]), int(seed[i]), int(ctr[i]), 1, int(off[i]), int(L[i]),
+                               int(lo[i]), int(hi[i]))
+        else:
+            ref = O.fill(int(gen[i]), int(dist[i]), int(seed[i]), int(ctr[i]), int(off[i]),
+                         int(L[i]))
+        assert np.array_equal(got, ref.view(np.uint32)), ("request", i, int(gen[i]), int(dist[i]))
+        assert host[starts[i] + L[i]] == 0xFFFFFFFF, ("guard overwritten after request", i)
+    return host
+
+
+def test_batched_integer_ranges(R, O):
+    """Integer-range requests inside a batch equal orng_fill_range of the same
+    stream and bounds (the oracle's), mixed with other distributions, with
+    outputs on every alignment, through the batched call, the allocation-free
+    call and the plain one-launch-per-request call."""
+    rng = np.random.default_rng(11)
+    batch = _range_mix(rng, 600)
+    print("batched integer ranges: 600 requests", flush=True)
+    a = _check_range_mix(R, O, batch, R.orng_fill_batched)
+    b = _check_range_mix(R, O, batch, R.orng_fill_each)
+    c = _check_range_mix(R, O, batch, R.orng_fill_batched_noalloc)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_batched_integer_ranges_long_and_tyche(R, O):
+    """Range requests that span many tiles (all ten generators, Tyche tiles
+    deep in a stream), under launch shapes that loop and that do not."""
+    rng = np.random.default_rng(12)
+    m = 20
+    gen = np.arange(m) % 10
+    dist = np.full(m, 5)
+    seed = rng.integers(0, 2**32, m, dtype=np.uint64)
+    ctr = rng.integers(0, 2**32, m, dtype=np.uint64)
+    L = rng.integers(100_000, 300_000, m)
+    off = rng.integers(0, 2**31 - 300_000, m).astype(np.uint64)
+    off[::4] = 8192 * 7 + 5                       # inside a Tyche tile, odd
+    lo = rng.integers(-2**31, 0, m).astype(np.int32)
+    hi = (lo.astype(np.int64) + rng.integers(1, 2**31, m)).astype(np.int32)
+    batch = (gen, dist, seed, ctr, off, L, lo, hi)
+    try:
+        for wg, mx in [(0, 0), (64, 1), (256, 7)]:
+            R.orng_set_launch(wg_size=wg, max_wgs=mx)
+            print("launch", wg, mx, flush=True)
+            _check_range_mix(R, O, batch, R.orng_fill_batched, pad=2)
+    finally:
+        R.orng_reset_launch()
+
+
+def test_batched_integer_range_errors(R):
+    buf = torch.empty(64, dtype=torch.int32, device="cuda")
+    p = buf.data_ptr()
+    with pytest.raises(R.OrngError) as e:      # lo >= hi
+        R.orng_fill_batched(R.make_requests(0, 5, 1, 1, 0, 16, p, 5, 5))
+    assert e.value.status == R.EINVAL
+    with pytest.raises(R.OrngError) as e:      # past the 2^31 samples of a stream
+        R.orng_fill_batched(R.make_requests(0, 5, 1, 1, 2**31 - 8, 16, p, 0, 9))
+    assert e.value.status == R.ERANGE
+    with pytest.raises(R.OrngError) as e:      # not a distribution
+        R.orng_fill_batched(R.make_requests(0, 6, 1, 1, 0, 16, p, 0, 9))
+    assert e.value.status == R.EINVAL
+    with pytest.raises(R.OrngError) as e:      # plain fills take no bounds
+        R.orng_fill(0, 5, 1, 1, 0, 16, buf)
+    assert e.value.status == R.EINVAL
+    R.orng_fill_batched(R.make_requests(0, 5, 1, 1, 2**31 - 16, 16, p, -3, 4))

@@ -408,3 +408,85 @@ def test_serve_saturated_trace_every_result(R, O):
                            (int(tr["offset"][i]) + js).astype(np.uint64))
         assert np.array_equal(got[k:k + js.size], exp.view(np.uint32)), ("request", i)
         k += js.size
+
+
+def _range_reqs(rng, m, lo_log2=10, hi_log2=16):
+    """Integer-range requests: every generator, bounds from one value to the
+    whole int32 span, offsets anywhere in the 2^31 samples of a stream."""
+    out = []
+    for k in range(m):
+        n = int(2 ** (lo_log2 + (hi_log2 - lo_log2) * rng.random()))
+        lo = int(rng.integers(-2**31, 2**31 - 1))
+        r = [2**32 - 1, 1, 6, int(2 ** rng.integers(1, 32)), int(rng.integers(1, 2**32))][k % 5]
+        lo = -2**31 if r == 2**32 - 1 else lo
+        hi = min(lo + r, 2**31 - 1)
+        q = dict(gen=int(rng.integers(0, 10)), dist=5, seed=int(rng.integers(0, 2**63)),
+                 ctr=int(rng.integers(0, 2**32)), offset=int(rng.integers(0, 2**31 - n)), n=n,
+                 lo=lo, hi=hi)
+        if q["gen"] == 9:
+            q["seed"] &= 0xFFFFFFFF
+        out.append(q)
+    return out
+
+
+def _ref(O, q):
+    if q["dist"] == 5:
+        return O.fill_range(q["gen"], q["seed"], q["ctr"], 1, q["offset"], q["n"], q["lo"],
+                            q["hi"]).view(np.uint32)
+    return O.fill(q["gen"], q["dist"], q["seed"], q["ctr"], q["offset"], q["n"]).view(np.uint32)
+
+
+def test_serve_integer_ranges(R, O):
+    """Integer-range requests served in a mix with other distributions, into
+    arena outputs and misaligned caller buffers, several steps per request:
+    each equals orng_fill_range of the same stream and bounds (the oracle's)
+    and the same request served alone."""
+    rng = np.random.default_rng(21)
+    qs = _range_reqs(rng, 40) + _random_reqs(rng, 40)
+    qs = [qs[i] for i in rng.permutation(len(qs))]
+    arena = _arena(32 << 20)
+    srv = R.orng_serve_create(arena.numel() * 4, arena=arena, step_words=1 << 16)
+    try:
+        bufs, tickets = [], []
+        for k, q in enumerate(qs):
+            if k % 3 == 0:  # caller buffer, one word off the 16-byte grid
+                b = torch.full((q["n"] + 2,), -1, dtype=torch.int32, device="cuda")
+                bufs.append(b)
+                tickets.append(R.orng_serve_submit(srv, out=b.data_ptr() + 4, **q))
+            else:
+                bufs.append(None)
+                tickets.append(R.orng_serve_submit(srv, **q))
+        for q, t, b in zip(qs, tickets, bufs):
+            res = R.orng_serve_wait(srv, t)
+            assert res["status"] == 0 and res["n"] == q["n"]
+            if b is None:
+                got = _read(arena, res)
+            else:
+                torch.cuda.synchronize()
+                host = b.cpu().numpy().view(np.uint32)
+                assert host[0] == 0xFFFFFFFF and host[-1] == 0xFFFFFFFF
+                got = host[1:1 + q["n"]]
+            assert np.array_equal(got, _ref(O, q)), q
+            R.orng_serve_release(srv, t)
+        # mix == alone for one range request
+        probe = _range_reqs(rng, 1, 16, 17)[0]
+        t = R.orng_serve_submit(srv, **probe)
+        alone = _read(arena, R.orng_serve_wait(srv, t)).copy()
+        R.orng_serve_release(srv, t)
+        others = _random_reqs(rng, 20) + _range_reqs(rng, 20)
+        ts = [R.orng_serve_submit(srv, **q) for q in others[:20]]
+        t = R.orng_serve_submit(srv, **probe)
+        ts += [R.orng_serve_submit(srv, **q) for q in others[20:]]
+        assert np.array_equal(_read(arena, R.orng_serve_wait(srv, t)), alone)
+        R.orng_serve_release(srv, t)
+        for x in ts:
+            R.orng_serve_wait(srv, x)
+            R.orng_serve_release(srv, x)
+        with pytest.raises(R.OrngError) as e:
+            R.orng_serve_submit(srv, 0, 5, 1, 1, 0, 16, lo=3, hi=3)
+        assert e.value.status == R.EINVAL
+        with pytest.raises(R.OrngError) as e:
+            R.orng_serve_submit(srv, 0, 5, 1, 1, 2**31 - 4, 16, lo=0, hi=3)
+        assert e.value.status == R.ERANGE
+    finally:
+        R.orng_serve_destroy(srv)

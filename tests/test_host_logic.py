@@ -109,11 +109,17 @@ def test_normal_pairs_validation(L):
 
 
 def _reqs(rows):
+    """orng_req_t records (56 bytes, the header's field order) from rows
+    (gen, dist, offset, n, out, flags[, lo, hi])."""
     dt = np.dtype([("seed", "<u8"), ("offset", "<u8"), ("n", "<u8"), ("out", "<u8"),
-                   ("ctr", "<u4"), ("gen", "<u4"), ("dist", "<u4"), ("flags", "<u4")])
+                   ("ctr", "<u4"), ("gen", "<u4"), ("dist", "<u4"), ("flags", "<u4"),
+                   ("lo", "<i4"), ("hi", "<i4")])
+    assert dt.itemsize == 56
     r = np.zeros(len(rows), dt)
-    for i, (gen, dist, off, n, out, flags) in enumerate(rows):
-        r[i] = (1, off, n, out, 2, gen, dist, flags)
+    for i, row in enumerate(rows):
+        gen, dist, off, n, out, flags = row[:6]
+        lo, hi = row[6:] if len(row) > 6 else (0, 0)
+        r[i] = (1, off, n, out, 2, gen, dist, flags, lo, hi)
     return r
 
 
@@ -122,7 +128,12 @@ def test_batched_validation_rejects_whole_batch(L, fn):
     f = getattr(L, fn)
     cases = [
         ([(0, 0, 0, 16, FAKE, 0), (10, 0, 0, 16, FAKE, 0)], EINVAL),    # bad generator
-        ([(0, 5, 0, 16, FAKE, 0)], EINVAL),                              # bad distribution
+        ([(0, 6, 0, 16, FAKE, 0)], EINVAL),                              # bad distribution
+        ([(0, 5, 0, 16, FAKE, 0, 7, 7)], EINVAL),                        # range, lo == hi
+        ([(0, 5, 0, 16, FAKE, 0, 8, -8)], EINVAL),                       # range, lo > hi
+        ([(0, 5, 2**31 - 8, 16, FAKE, 0, 0, 9)], ERANGE),                # range past 2^31
+        ([(0, 5, 0, 16, FAKE + 2, 0, 0, 9)], EINVAL),                    # range, misaligned
+        ([(9, 5, 0, 16, FAKE, 0, -2**31, 2**31 - 1), (9, 5, 0, 16, FAKE, 0, 0, 0)], EINVAL),
         ([(0, 0, 0, 16, FAKE, 1)], EINVAL),                              # reserved flags
         ([(0, 0, 2**32 - 8, 16, FAKE, 0)], ERANGE),                      # past the period
         ([(0, 0, 0, 16, 0, 0)], EINVAL),                                 # NULL output
