@@ -97,7 +97,10 @@ enum {
  *   Threefry4x32-13, Threefry2x64-13: as their 20-round forms, with the
  *                    key injections after rounds 4, 8 and 12 and 13 rounds
  *   Squares32      : squares32(counter (ctr << 32) | p, key K(seed)),
- *                    K = SplitMix64 output step of seed, low bit set
+ *                    K = SplitMix64 output step of seed, low bit set (two
+ *                    seeds per key: those whose SplitMix64 outputs differ
+ *                    only in bit 0; below 2^32 only 369106595 and
+ *                    2888123536 pair up)
  *   Tyche          : tiles of 16384 words; word p of tile t = p / 16384,
  *                    r = p % 16384 is output 4*(r/256) + r%4 of the Tyche
  *                    instance seeded with (seed, ctr) whose c word is XORed

@@ -274,3 +274,15 @@ def test_grid_stride_sweep(R, O, gen):
             assert np.array_equal(as_u32(m), ref), (gen, "multi", cap)
     finally:
         R.orng_reset_launch()
+
+
+def test_squares_seed_pair_shares_streams(R, O):
+    """The one pair of 32-bit seeds with the same Squares key (the key map is
+    two-to-one) gives the same Squares32 and Squares64 words on the GPU."""
+    a, b = 369106595, 2888123536
+    for gen in (3, 8):
+        x = R.fill(gen, 0, a, 5, 1, 10001)
+        y = R.fill(gen, 0, b, 5, 1, 10001)
+        torch.cuda.synchronize()
+        assert torch.equal(x, y)
+        assert np.array_equal(x.cpu().numpy().view(np.uint32), O.fill(gen, 0, b, 5, 1, 10001))
