@@ -48,9 +48,12 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) {
 // Output writer of one span.  delta = (output address in words - p0) mod 4.
 // delta == 0: block b maps onto one 16-byte chunk.  delta != 0: the chunk
 // that holds the head of block b also holds the last delta words of block
-// b - 1; lane l takes them from lane l - 1 (cross-lane shift) and lane 0 from
-// lane 63 of the previous iteration (carried in uniform registers), so every
-// interior chunk is still one 16-byte store.  Lane 63 writes its block's tail
+// b - 1; lane l takes them from lane l - 1 and lane 0 from lane 63 of the
+// previous iteration (carried in uniform registers), so every interior chunk
+// is still one 16-byte store.  The shift is a DPP whole-wave shift right by
+// one lane (a VALU move; lane 0, which has no source lane, keeps the `old`
+// operand, the carry): on MI355X the LDS permute it replaces put a wait for
+// the LDS unit between every block and its store.  Lane 63 writes its block's tail
 // itself when no further iteration of the span follows; lane 0 of the first
 // iteration writes only its own words.  Positions outside [p0, pend) are never
 // written.
@@ -78,10 +81,9 @@ __device__ __forceinline__ void emit_block(SpanOut &o, uint64_t b, const uint32_
     const int d = (int)o.delta;
     uint32_t prev[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        prev[j] = __shfl_up(w[j], 1, 64);
-        if (lane == 0) prev[j] = o.carry[j];
-    }
+    for (int j = 0; j < 4; ++j)  // wave_shr:1, all rows and banks, no bound_ctrl
+        prev[j] = (uint32_t)__builtin_amdgcn_update_dpp((int)o.carry[j], (int)w[j], 0x138, 0xF,
+                                                        0xF, false);
     const bool prev_ok = lane > 0 || o.have_carry;
     const int64_t q0 = (int64_t)(b * 4) - d;  // first position of the chunk
     // chunk word j (position q0 + j) comes from the previous block if j < d.
@@ -126,6 +128,7 @@ __device__ __forceinline__ void process_span(const KeySched &ks, uint32_t ctr, c
     o.pend = pend;
     o.delta = delta;
     o.have_carry = false;
+    o.carry[0] = o.carry[1] = o.carry[2] = o.carry[3] = 0;
     // Counter generators: where the next iteration's block is also in range,
     // two blocks are made and converted before either is emitted; their work
     // is independent, which gives the scheduler twice the instruction-level

@@ -411,7 +411,7 @@ int orng_autotune(int gen, int dist, const char *cache_path) {
         uint64_t len = (uint64_t)std::pow(2.0, u);
         if (len < 1) len = 1;
         if (used + len * kw > n) break;
-        orng_req_t r;
+        orng_req_t r{};
         r.seed = rng();
         r.ctr = (uint32_t)rng();
         r.offset = rng() % (lim - len + 1);

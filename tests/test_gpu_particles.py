@@ -45,3 +45,20 @@ def test_particle_streams_paper_shape_sampled(R, O, gen):
     for t in [0, T - 1] + list(rng.integers(0, T, 3)):
         ref = O.particle_streams(gen, 1, P, D, 1 + int(t), 1).reshape(P, D)
         assert np.array_equal(got[t], ref), t
+
+
+@pytest.mark.parametrize("gen", [0, 3, 4, 8, 9])
+@pytest.mark.parametrize("shift", [1, 2, 3])
+@pytest.mark.parametrize("draws", [1, 3, 5, 16])
+def test_particle_streams_misaligned_output(R, O, gen, shift, draws):
+    """Outputs 1-3 words off the 16-byte grid (the wave slices are stored in
+    16-byte chunks at the output's own phase): same words, nothing written
+    before or after the output."""
+    P, T = 333, 5
+    n = P * draws * T
+    buf = torch.full((n + shift + 1,), -1, dtype=torch.int32, device="cuda")
+    R.orng_particle_streams(gen, 7, P, draws, 11, T, buf.data_ptr() + 4 * shift)
+    torch.cuda.synchronize()
+    host = buf.cpu().numpy().view(np.uint32)
+    assert np.all(host[:shift] == 0xFFFFFFFF) and host[shift + n] == 0xFFFFFFFF
+    assert np.array_equal(host[shift:shift + n], O.particle_streams(gen, 7, P, draws, 11, T))
