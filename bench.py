@@ -59,10 +59,16 @@ SLOTS_GEN = {0: 38 / 4, 1: 128 / 4, 2: 109 / 4, 3: 13 + 3 / 4, 4: 12 + 20 * 12 /
              5: 80 / 4, 6: 70 / 4, 7: 12 + 20 * 12 / 256, 8: (5 * 3 + 2 + 1) / 2 + 3 / 4,
              9: 10.0}
 SLOTS_DIST = {0: 0.0, 1: 2.0, 2: 36.5 / 2}
-# Fused walk, per particle, step and coordinate: one Philox word (9.5 slots),
-# one Box-Muller sample (half a pair, 18.25) and the fmaf update (an fp32
-# operation, 0.5): 28.25 slots; 84.75 per particle-step in 3-D.
-WALK_SLOTS_PER_DIM = 38 / 4 + 36.5 / 2 + 0.5
+# Fused walk, per particle, step and coordinate: one Philox word, one
+# Box-Muller sample (half a pair, 18.25) and the fmaf update (an fp32
+# operation, 0.5).  The walk's Philox counter is (block, ctr0 + particle, 0,
+# 0): the block index is the same for every lane of a wave (all particles are
+# at the same step), so more of the first rounds is uniform than in a fill
+# (whose block index varies by lane): round 1 leaves one vector xor, round 2 one
+# product and one xor3, round 3 one product and two xor3, rounds 4-10 two of
+# each: 34 slots per block, 8.5 per word.  27.25 slots; 81.75 per
+# particle-step in 3-D.
+WALK_SLOTS_PER_DIM = 34 / 4 + 36.5 / 2 + 0.5
 # float64 uniform: two words per sample, then shift, two conversions, one
 # exact fma and one scaling (float64 operations: one slot each at the
 # published 78.6 TFLOP/s vector rate); 8 bytes written per sample
@@ -103,21 +109,22 @@ def roofs(gen, dist, n, ms):
 # calibration factors a 1 GiB device copy gives for each counter.  Valid only
 # for the kernel sources and launch table they were measured on: bench.py
 # reports null traffic when the hash of those sources differs.
-TRAFFIC_SRC_SHA = "7c45a135ad260bf3"
-TRAFFIC_FACTORS = (1.999922278563641, 1.0)  # FETCH, WRITE
+TRAFFIC_SRC_SHA = "b7368a3e87beb1ea"
+TRAFFIC_FACTORS = (1.9999215633637493, 1.0)  # FETCH, WRITE
 TRAFFIC_KIB = {
-    (0, 0): (80.75, 4194304.0), (0, 1): (50.5, 4194321.25), (0, 2): (83.75, 4194327.125), (0, 3): (49.0, 4194304.0),
-    (0, 4): (70.5, 4194331.75), (1, 0): (54.0, 4194318.5), (1, 1): (59.25, 4194328.75), (1, 2): (63.875, 4194304.0),
-    (1, 3): (51.5, 4194324.125), (1, 4): (75.0, 4194304.125), (2, 0): (55.5, 4194318.125), (2, 1): (59.25, 4194354.5),
-    (2, 2): (63.75, 4194304.0), (2, 3): (55.0, 4194307.0), (2, 4): (82.1875, 4194304.0), (3, 0): (51.5, 4194304.0),
-    (3, 1): (45.0, 4194304.0), (3, 2): (106.1875, 4194329.375), (3, 3): (53.0, 4195101.25), (3, 4): (73.5, 4194321.875),
-    (4, 0): (38.6875, 4194304.0), (4, 1): (30.6875, 4194304.0), (4, 2): (38.125, 4194304.0), (4, 3): (66.6875, 4194304.0),
-    (4, 4): (40.5, 4194351.375), (5, 0): (43.0, 4194547.25), (5, 1): (54.0, 4194324.375), (5, 2): (59.0, 4194353.125),
-    (5, 3): (50.0, 4194913.0), (5, 4): (69.5, 4194312.125), (6, 0): (53.0, 4194304.0), (6, 1): (50.0, 4195179.875),
-    (6, 2): (57.5, 4194378.125), (6, 3): (51.5, 4195270.375), (6, 4): (76.5, 4194310.625), (7, 0): (25.0, 4194304.0),
-    (7, 1): (29.0, 4194304.0), (7, 2): (36.5, 4194386.5), (7, 3): (29.5, 4194304.0), (7, 4): (43.5, 4194304.0),
-    (8, 0): (48.0, 4197750.25), (8, 1): (50.5, 4194304.0), (8, 2): (54.5, 4194376.375), (8, 3): (49.0, 4195111.375),
-    (8, 4): (68.0, 4194329.625),
+    (0, 0): (80.125, 4194304.0), (0, 1): (45.0, 4194390.5), (0, 2): (93.625, 4194335.375), (0, 3): (50.0, 4194304.0),
+    (0, 4): (75.0, 4194323.28125), (1, 0): (55.8125, 4194316.0), (1, 1): (60.0625, 4194307.625), (1, 2): (71.75, 4194304.0),
+    (1, 3): (53.578125, 4194323.21875), (1, 4): (76.0, 4194306.25), (2, 0): (56.0, 4194336.125), (2, 1): (55.0, 4194318.25),
+    (2, 2): (71.1875, 4194304.0), (2, 3): (54.0, 4194336.65625), (2, 4): (82.265625, 4194304.0), (3, 0): (51.125, 4194348.75),
+    (3, 1): (50.6875, 4194358.75), (3, 2): (74.375, 4194319.875), (3, 3): (42.5, 4195463.5625), (3, 4): (68.0, 4194317.34375),
+    (4, 0): (30.25, 4194304.0), (4, 1): (31.25, 4194304.0), (4, 2): (34.3125, 4194323.125), (4, 3): (33.875, 4194304.0),
+    (4, 4): (43.015625, 4194315.5), (5, 0): (46.0, 4195287.75), (5, 1): (49.5, 4195496.8125), (5, 2): (56.0, 4194338.3125),
+    (5, 3): (43.0, 4196488.8125), (5, 4): (68.5, 4194310.0625), (6, 0): (50.5, 4194304.0), (6, 1): (50.0, 4196802.15625),
+    (6, 2): (61.0, 4194328.59375), (6, 3): (53.0, 4196025.53125), (6, 4): (73.0, 4194310.78125), (7, 0): (31.015625, 4194304.0),
+    (7, 1): (29.0, 4194304.0), (7, 2): (33.515625, 4194378.3125), (7, 3): (31.0, 4194304.0), (7, 4): (42.59375, 4194320.21875),
+    (8, 0): (36.5, 4196928.375), (8, 1): (50.0, 4194304.0), (8, 2): (60.0, 4194380.625), (8, 3): (50.0, 4196928.09375),
+    (8, 4): (71.5, 4194318.28125), (9, 0): (48.5, 4194304.0), (9, 1): (52.0, 4194304.0), (9, 2): (60.0, 4194346.71875),
+    (9, 3): (45.0, 4194304.0), (9, 4): (74.5, 4194325.125),
 }
 
 
