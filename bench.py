@@ -203,11 +203,44 @@ def cpu_baseline(seed, target_s=30.0):
         for d in range(3):
             assert L.oracle_fill(g, d, seed, 0, 0, per, buf_u.ctypes.data, th) == 0
     dt = time.perf_counter() - t0
-    return {"value": round(15 * per / dt / 1e9, 4), "unit": "GSamples/s", "cores": th,
-            "kind": "oracle", "nproc": os.cpu_count(), "cpu_model": cpu_model(),
-            "build": "g++ " + " ".join(O.NATIVE_FLAGS) + " -ffp-contract=off",
-            "sample": "first %d samples of each of the 15 fills (gen x dist), %.1f s wall"
-                      % (per, dt)}
+    res = {"value": round(15 * per / dt / 1e9, 4), "unit": "GSamples/s", "cores": th,
+           "kind": "oracle", "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+           "build": "g++ " + " ".join(O.NATIVE_FLAGS) + " -ffp-contract=off",
+           "sample": "first %d samples of each of the 15 fills (gen x dist), %.1f s wall"
+                     % (per, dt)}
+    # the plain multi-stream fill in full (2^20 streams x 4 words, u32 and f32 uniform)
+    from paper_2310_19925_amd import inputs
+    ns, ps = inputs.PLAIN_STREAMS, inputs.PLAIN_PER_STREAM
+    buf_m = np.empty(ns * ps, np.uint32)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        for d in (0, 1):
+            assert L.oracle_fill_multi(0, d, inputs.PLAIN_SEED, 0, ns, 0, ps,
+                                       buf_m.ctypes.data, th) == 0
+    t_m = (time.perf_counter() - t0) / 10
+    res["plain_multi"] = {"ms": round(t_m * 1e3, 3),
+                          "gsamples_s": round(ns * ps / t_m / 1e9, 4),
+                          "sample": "whole fill, u32 and f32 uniform, 5 runs each"}
+    # the walk on a subset of the particles (65,536 of 2^24), for as many of the 10^4
+    # steps as fit about 4 s, reported per particle-step (extrapolated to the full walk)
+    count, dim = 65536, 3
+    sig = (np.float32(1e-3), np.float32(1.0))
+
+    def walk(steps):
+        pos = np.zeros((dim, count), np.float32)
+        t = time.perf_counter()
+        assert L.oracle_brownian(seed, 0, None, count, dim, 0, steps, sig[0], sig[1],
+                                 pos.ctypes.data, None, 0, th) == 0
+        return time.perf_counter() - t
+    t_w = walk(50)
+    steps = max(50, min(10000, int(50 * 4.0 / max(t_w, 1e-3))))
+    t_w = walk(steps)
+    ps_rate = count * steps / t_w
+    res["walk"] = {"particle_steps_per_s": round(ps_rate, 1),
+                   "full_walk_s_extrapolated": round(2**24 * 10000 / ps_rate, 1),
+                   "sample": "%d particles x %d steps (3-D), %.1f s wall; extrapolated per "
+                             "particle-step" % (count, steps, t_w)}
+    return res
 
 
 def _time_events(stream, fn, reps):
