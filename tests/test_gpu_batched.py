@@ -308,3 +308,58 @@ def test_batched_integer_range_errors(R):
         R.orng_fill(0, 5, 1, 1, 0, 16, buf)
     assert e.value.status == R.EINVAL
     R.orng_fill_batched(R.make_requests(0, 5, 1, 1, 2**31 - 16, 16, p, -3, 4))
+
+
+def test_batched_ranges_with_float64_normals(R, O):
+    """A batch that holds integer ranges and float64 normals (the kernel variant
+    with both sets of cases): float64 outputs on 8-byte boundaries, int32
+    outputs one word off the 16-byte grid, a guard word before every output,
+    under the static and the persistent schedules."""
+    rng = np.random.default_rng(13)
+    m = 120
+    gen = rng.integers(0, 10, m)
+    dist = np.array([[5, 4, 3, 0, 5, 2][i % 6] for i in range(m)])
+    seed = rng.integers(0, 2**32, m, dtype=np.uint64)
+    ctr = rng.integers(0, 2**32, m, dtype=np.uint64)
+    L = np.maximum(1, np.floor(2.0 ** (15 * rng.random(m)))).astype(np.int64)
+    off = rng.integers(0, 2**31 - 2**15, m).astype(np.uint64)
+    lo = rng.integers(-2**31, 0, m).astype(np.int32)
+    hi = (lo.astype(np.int64) + rng.integers(1, 2**31, m)).astype(np.int32)
+    words = np.where((dist == 3) | (dist == 4), 2 * L, L)  # output words per request
+    starts = np.zeros(m, np.int64)
+    end = 0
+    for i in range(m):
+        s0 = end + 1                        # at least one guard word
+        if dist[i] in (3, 4):
+            s0 += s0 % 2                    # 8-byte aligned
+        elif dist[i] == 5:
+            s0 += (1 - s0 % 4) % 4          # one word past a 16-byte boundary
+        starts[i] = s0
+        end = s0 + words[i]
+    buf = torch.full((end + 1,), -1, dtype=torch.int32, device="cuda")
+    assert buf.data_ptr() % 16 == 0
+    reqs = R.make_requests(gen, dist, seed, ctr, off, L, buf.data_ptr() + 4 * starts, lo, hi)
+    written = np.zeros(end + 1, bool)
+    for i in range(m):
+        written[starts[i]:starts[i] + words[i]] = True
+    try:
+        for wg, mx in [(0, 0), (256, 5)]:
+            print("launch", wg, mx, flush=True)
+            R.orng_set_launch(wg_size=wg, max_wgs=mx)
+            buf.fill_(-1)
+            R.orng_fill_batched(reqs)
+            torch.cuda.synchronize()
+            host = buf.cpu().numpy().view(np.uint32)
+            for i in range(m):
+                got = host[starts[i]:starts[i] + words[i]]
+                if dist[i] == 5:
+                    ref = O.fill_range(int(gen[i]), int(seed[i]), int(ctr[i]), 1, int(off[i]),
+                                       int(L[i]), int(lo[i]), int(hi[i]))
+                else:
+                    ref = O.fill(int(gen[i]), int(dist[i]), int(seed[i]), int(ctr[i]),
+                                 int(off[i]), int(L[i]))
+                assert np.array_equal(got, ref.view(np.uint32)), ("request", i, int(gen[i]),
+                                                                  int(dist[i]), wg, mx)
+            assert np.all(host[~written] == 0xFFFFFFFF)  # nothing outside the outputs
+    finally:
+        R.orng_reset_launch()

@@ -442,17 +442,21 @@ def test_serve_integer_ranges(R, O):
     each equals orng_fill_range of the same stream and bounds (the oracle's)
     and the same request served alone."""
     rng = np.random.default_rng(21)
-    qs = _range_reqs(rng, 40) + _random_reqs(rng, 40)
+    f64 = [dict(q, dist=4 if k % 2 else 3, offset=max(0, q["offset"] // 2 - q["n"]))
+           for k, q in enumerate(_random_reqs(rng, 10))]  # float64 in the same steps
+    qs = _range_reqs(rng, 40) + _random_reqs(rng, 40) + f64
     qs = [qs[i] for i in rng.permutation(len(qs))]
     arena = _arena(32 << 20)
     srv = R.orng_serve_create(arena.numel() * 4, arena=arena, step_words=1 << 16)
     try:
         bufs, tickets = [], []
         for k, q in enumerate(qs):
-            if k % 3 == 0:  # caller buffer, one word off the 16-byte grid
-                b = torch.full((q["n"] + 2,), -1, dtype=torch.int32, device="cuda")
-                bufs.append(b)
-                tickets.append(R.orng_serve_submit(srv, out=b.data_ptr() + 4, **q))
+            w = 2 * q["n"] if q["dist"] in (3, 4) else q["n"]  # output words
+            if k % 3 == 0:  # caller buffer, one word off the 16-byte grid (two for float64)
+                sh = 2 if q["dist"] in (3, 4) else 1
+                b = torch.full((w + sh + 1,), -1, dtype=torch.int32, device="cuda")
+                bufs.append((b, sh, w))
+                tickets.append(R.orng_serve_submit(srv, out=b.data_ptr() + 4 * sh, **q))
             else:
                 bufs.append(None)
                 tickets.append(R.orng_serve_submit(srv, **q))
@@ -460,12 +464,16 @@ def test_serve_integer_ranges(R, O):
             res = R.orng_serve_wait(srv, t)
             assert res["status"] == 0 and res["n"] == q["n"]
             if b is None:
-                got = _read(arena, res)
-            else:
+                w = 2 * q["n"] if q["dist"] in (3, 4) else q["n"]
+                off = (res["d_out"] - arena.data_ptr()) // 4
                 torch.cuda.synchronize()
-                host = b.cpu().numpy().view(np.uint32)
-                assert host[0] == 0xFFFFFFFF and host[-1] == 0xFFFFFFFF
-                got = host[1:1 + q["n"]]
+                got = arena[off:off + w].cpu().numpy().view(np.uint32)
+            else:
+                buf, sh, w = b
+                torch.cuda.synchronize()
+                host = buf.cpu().numpy().view(np.uint32)
+                assert np.all(host[:sh] == 0xFFFFFFFF) and host[-1] == 0xFFFFFFFF
+                got = host[sh:sh + w]
             assert np.array_equal(got, _ref(O, q)), q
             R.orng_serve_release(srv, t)
         # mix == alone for one range request
