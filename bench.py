@@ -109,22 +109,22 @@ def roofs(gen, dist, n, ms):
 # calibration factors a 1 GiB device copy gives for each counter.  Valid only
 # for the kernel sources and launch table they were measured on: bench.py
 # reports null traffic when the hash of those sources differs.
-TRAFFIC_SRC_SHA = "b7368a3e87beb1ea"
-TRAFFIC_FACTORS = (1.9999215633637493, 1.0)  # FETCH, WRITE
+TRAFFIC_SRC_SHA = "02ad80091588932f"
+TRAFFIC_FACTORS = (1.9999220401636202, 1.0)  # FETCH, WRITE
 TRAFFIC_KIB = {
-    (0, 0): (80.125, 4194304.0), (0, 1): (45.0, 4194390.5), (0, 2): (93.625, 4194335.375), (0, 3): (50.0, 4194304.0),
-    (0, 4): (75.0, 4194323.28125), (1, 0): (55.8125, 4194316.0), (1, 1): (60.0625, 4194307.625), (1, 2): (71.75, 4194304.0),
-    (1, 3): (53.578125, 4194323.21875), (1, 4): (76.0, 4194306.25), (2, 0): (56.0, 4194336.125), (2, 1): (55.0, 4194318.25),
-    (2, 2): (71.1875, 4194304.0), (2, 3): (54.0, 4194336.65625), (2, 4): (82.265625, 4194304.0), (3, 0): (51.125, 4194348.75),
-    (3, 1): (50.6875, 4194358.75), (3, 2): (74.375, 4194319.875), (3, 3): (42.5, 4195463.5625), (3, 4): (68.0, 4194317.34375),
-    (4, 0): (30.25, 4194304.0), (4, 1): (31.25, 4194304.0), (4, 2): (34.3125, 4194323.125), (4, 3): (33.875, 4194304.0),
-    (4, 4): (43.015625, 4194315.5), (5, 0): (46.0, 4195287.75), (5, 1): (49.5, 4195496.8125), (5, 2): (56.0, 4194338.3125),
-    (5, 3): (43.0, 4196488.8125), (5, 4): (68.5, 4194310.0625), (6, 0): (50.5, 4194304.0), (6, 1): (50.0, 4196802.15625),
-    (6, 2): (61.0, 4194328.59375), (6, 3): (53.0, 4196025.53125), (6, 4): (73.0, 4194310.78125), (7, 0): (31.015625, 4194304.0),
-    (7, 1): (29.0, 4194304.0), (7, 2): (33.515625, 4194378.3125), (7, 3): (31.0, 4194304.0), (7, 4): (42.59375, 4194320.21875),
-    (8, 0): (36.5, 4196928.375), (8, 1): (50.0, 4194304.0), (8, 2): (60.0, 4194380.625), (8, 3): (50.0, 4196928.09375),
-    (8, 4): (71.5, 4194318.28125), (9, 0): (48.5, 4194304.0), (9, 1): (52.0, 4194304.0), (9, 2): (60.0, 4194346.71875),
-    (9, 3): (45.0, 4194304.0), (9, 4): (74.5, 4194325.125),
+    (0, 0): (79.375, 4194304.0), (0, 1): (45.5, 4194651.125), (0, 2): (84.1875, 4194339.625), (0, 3): (50.0, 4194304.0),
+    (0, 4): (75.0, 4194320.84375), (1, 0): (55.875, 4194318.25), (1, 1): (60.5, 4194305.25), (1, 2): (72.125, 4194304.0),
+    (1, 3): (53.5625, 4194316.15625), (1, 4): (76.0, 4194305.09375), (2, 0): (38.0, 4194314.375), (2, 1): (42.0, 4194332.375),
+    (2, 2): (81.0, 4194304.0), (2, 3): (45.5, 4194318.5), (2, 4): (59.0, 4194304.0), (3, 0): (37.5, 4194336.5),
+    (3, 1): (39.0, 4194304.0), (3, 2): (76.125, 4194318.25), (3, 3): (39.0, 4197170.75), (3, 4): (49.0, 4194319.03125),
+    (4, 0): (25.75, 4194304.0), (4, 1): (32.5625, 4194304.0), (4, 2): (42.875, 4194304.0), (4, 3): (38.21875, 4194304.0),
+    (4, 4): (40.046875, 4194314.59375), (5, 0): (51.0, 4195648.65625), (5, 1): (43.0, 4195093.40625), (5, 2): (58.0, 4194329.4375),
+    (5, 3): (52.5, 4196602.84375), (5, 4): (72.5, 4194312.78125), (6, 0): (44.5, 4194304.0), (6, 1): (52.5, 4195981.875),
+    (6, 2): (53.5, 4194327.8125), (6, 3): (40.0, 4197866.53125), (6, 4): (71.0, 4194311.5625), (7, 0): (31.171875, 4194304.0),
+    (7, 1): (31.703125, 4194304.0), (7, 2): (29.015625, 4194543.125), (7, 3): (29.53125, 4194304.0), (7, 4): (43.109375, 4194313.59375),
+    (8, 0): (34.0, 4197338.0625), (8, 1): (27.5, 4194304.0), (8, 2): (50.0, 4194368.15625), (8, 3): (35.5, 4196393.34375),
+    (8, 4): (63.0, 4194316.34375), (9, 0): (43.0, 4194304.0), (9, 1): (52.0, 4194304.0), (9, 2): (61.5, 4194313.84375),
+    (9, 3): (46.0, 4194304.0), (9, 4): (69.0, 4194325.59375),
 }
 
 

@@ -34,6 +34,26 @@ struct SpanArgs {
     uint32_t delta;            // (stream 0 output address in words - p0) mod 4
 };
 
+// Fill kernels that take the check-free loop for interior spans (see
+// process_span).  Measured on MI355X (2^30-sample fills, 2^29 for float64,
+// two builds interleaved): Squares32 u32 / uniform 1-9% faster, Threefry2x64
+// 3-10% (float64 normals 10%), Squares64 2-7%, Tyche and Tyche-i u32 /
+// uniform / float64 uniform 2-4%, the 13-round Threefry2x64 normals 3-10%;
+// slower or unchanged, so left out: Threefry4x32 (38 -> 62 VGPRs, 8-10%
+// slower), Philox, Philox2x32, Tyche normals, 13-round Threefry2x64 u32 /
+// uniform (2-7% slower).
+template <int G, int D>
+constexpr bool fast_span() {
+    if constexpr (G == G_TF2X64 || G == G_SQUARES || G == G_SQUARES64)
+        return true;
+    else if constexpr (G == G_TF2X64_13)
+        return D != D_U32 && D != D_UNIFORM;
+    else if constexpr (tyche_like(G))
+        return D != D_NORMAL && D != D_F64N;
+    else
+        return false;
+}
+
 template <int G, int D, bool NT>
 __global__ __launch_bounds__(512) void k_span(SpanArgs a) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -51,7 +71,8 @@ __global__ __launch_bounds__(512) void k_span(SpanArgs a) {
         const uint32_t ctr = a.ctr0 + (uint32_t)si;
         char *base = a.out + si * a.n * 4;
         const uint32_t delta = (a.delta + (uint32_t)(si * a.n)) & 3u;
-        process_span<G, D, NT>(a.ks, ctr, base, a.p0, pend, span, a.unroll, delta, lane);
+        process_span<G, D, NT, fast_span<G, D>()>(a.ks, ctr, base, a.p0, pend, span, a.unroll,
+                                                  delta, lane);
     }
 }
 

@@ -118,7 +118,11 @@ __device__ __forceinline__ void emit_block(SpanOut &o, uint64_t b, const uint32_
     o.have_carry = true;
 }
 
-template <int G, int D, bool NT>
+// FAST: compile in the check-free loop for spans wholly inside the range on
+// the block grid (the plain fill kernel); the batched and served kernels,
+// whose outputs are mostly off the grid, leave it out to keep their register
+// counts (34 instead of 58-59 VGPRs).
+template <int G, int D, bool NT, bool FAST = false>
 __device__ __forceinline__ void process_span(const KeySched &ks, uint32_t ctr, char *base,
                                              uint64_t p0, uint64_t pend, uint64_t span,
                                              uint32_t unroll, uint32_t delta, uint32_t lane) {
@@ -135,10 +139,28 @@ __device__ __forceinline__ void process_span(const KeySched &ks, uint32_t ctr, c
     // parallelism (four Box-Muller pairs instead of two; the Threefry4x32
     // normal fill gains ~5% on MI355X).  Emission stays in block order.  Tyche's
     // words come from one sequential state, so it keeps one block per step.
+    // A span wholly inside [p0, pend) whose output lies on the block grid
+    // (delta == 0) -- every span of an aligned fill but its first and last --
+    // takes a loop with no per-block range checks or carries: the store
+    // address steps by 1 KiB per iteration.  On MI355X the checks and 64-bit
+    // address arithmetic of the general path cost ~3.5 instructions per word,
+    // a quarter of a Squares32 word's arithmetic.
     if constexpr (tyche_like(G)) {
         TycheT<G == G_TYCHE_I> st;
         st.seed(ks, (uint32_t)span * 64u + lane, ctr);
         const uint64_t tile_block = span * TYCHE_TILE_BLOCKS;
+        if (FAST && delta == 0 && tile_block * 4 >= p0 &&
+            (tile_block + TYCHE_TILE_BLOCKS) * 4 <= pend) {
+            char *q = base + 4 * ((tile_block + lane) * 4 - p0);
+            for (uint32_t k = 0; k < 64; ++k) {
+                uint32_t w[4];
+                st.next4(w);
+                convert4<D>(w);
+                store16<NT>(q, w);
+                q += 1024;
+            }
+            return;
+        }
         for (uint32_t k = 0; k < 64; ++k) {
             const uint64_t bw = tile_block + 64u * k;
             if (bw * 4 >= pend) break;
@@ -154,6 +176,29 @@ __device__ __forceinline__ void process_span(const KeySched &ks, uint32_t ctr, c
         }
     } else {
         const uint64_t b0 = span * 64u * unroll;
+        if (FAST && delta == 0 && b0 * 4 >= p0 && (b0 + 64u * unroll) * 4 <= pend) {
+            char *q = base + 4 * ((b0 + lane) * 4 - p0);
+            uint32_t b = (uint32_t)(b0 + lane);
+            uint32_t u = 0;
+            for (; u + 1 < unroll; u += 2) {
+                uint32_t w[4], w2[4];
+                counter_block<G>(b, ctr, ks, w);
+                counter_block<G>(b + 64u, ctr, ks, w2);
+                convert4<D>(w);
+                convert4<D>(w2);
+                store16<NT>(q, w);
+                store16<NT>(q + 1024, w2);
+                q += 2048;
+                b += 128u;
+            }
+            if (u < unroll) {
+                uint32_t w[4];
+                counter_block<G>(b, ctr, ks, w);
+                convert4<D>(w);
+                store16<NT>(q, w);
+            }
+            return;
+        }
         for (uint32_t u = 0; u < unroll;) {
             const uint64_t bw = b0 + 64u * u;
             if (bw * 4 >= pend) break;

@@ -276,6 +276,43 @@ def test_grid_stride_sweep(R, O, gen):
         R.orng_reset_launch()
 
 
+@pytest.mark.parametrize("gen", range(10))
+def test_aligned_interior_spans_sweep(R, O, gen):
+    """Outputs on the block grid from block-aligned offsets, so that every span
+    but the first and last is wholly inside the range (the fill kernel's
+    check-free loop where it is compiled in): each distribution under the
+    tuned launch and with the grid capped at 1 and 7 workgroups (every wave
+    loops over many such spans), and a multi-stream fill of 37 aligned
+    streams, element by element against the oracle, with nothing written
+    around the output."""
+    seed = key32(gen, 0xD1B54A32D192ED03)
+    n = (1 << 20) + 4 * 777
+    try:
+        for cap in (0, 1, 7):
+            R.orng_set_launch(max_wgs=cap)
+            for dist in range(5):
+                k = 2 if dist >= 3 else 1
+                off = 16384 * 3 + 4 * 5 if k == 1 else 8192 * 3 + 2 * 5  # block-aligned
+                print("aligned gen=%d dist=%d cap=%d" % (gen, dist, cap), flush=True)
+                buf = torch.full((n * k + 8,), -1, dtype=torch.int32, device="cuda")
+                out = buf[4:4 + n * k]
+                assert out.data_ptr() % 16 == 0
+                R.orng_fill(gen, dist, seed, 12, off, n, out)
+                torch.cuda.synchronize()
+                got = as_u32(buf)
+                ref = bits(O.fill(gen, dist, seed, 12, off, n))
+                assert np.array_equal(got[4:4 + n * k], ref), (gen, dist, cap)
+                assert np.all(got[:4] == 0xFFFFFFFF) and np.all(got[4 + n * k:] == 0xFFFFFFFF)
+            per, ns = 20480, 37
+            m = torch.full((ns * per,), -1, dtype=torch.int32, device="cuda")
+            R.orng_fill_multi(gen, 1, seed, 9, ns, 4096, per, m)
+            torch.cuda.synchronize()
+            ref = bits(O.fill_multi(gen, 1, seed, 9, ns, 4096, per))
+            assert np.array_equal(as_u32(m), ref), (gen, "multi", cap)
+    finally:
+        R.orng_reset_launch()
+
+
 def test_squares_seed_pair_shares_streams(R, O):
     """The one pair of 32-bit seeds with the same Squares key (the key map is
     two-to-one) gives the same Squares32 and Squares64 words on the GPU."""
