@@ -35,23 +35,31 @@ struct SpanArgs {
 };
 
 // Fill kernels that take the check-free loop for interior spans (see
-// process_span).  Measured on MI355X (2^30-sample fills, 2^29 for float64,
-// two builds interleaved): Squares32 u32 / uniform 1-9% faster, Threefry2x64
-// 3-10% (float64 normals 10%), Squares64 2-7%, Tyche and Tyche-i u32 /
-// uniform / float64 uniform 2-4%, the 13-round Threefry2x64 normals 3-10%;
-// slower or unchanged, so left out: Threefry4x32 (38 -> 62 VGPRs, 8-10%
-// slower), Philox, Philox2x32, Tyche normals, 13-round Threefry2x64 u32 /
-// uniform (2-7% slower).
+// process_span): 1 with two blocks per iteration, 2 with one, 0 the general
+// loop only.  Measured on MI355X (2^30-sample fills, 2^29 for float64, builds
+// interleaved on one box): two blocks per iteration made Squares32 u32 /
+// uniform 1-9% faster, Threefry2x64 3-10% (float64 normals 10%), Squares64
+// 2-7%, Tyche and Tyche-i u32 / uniform / float64 uniform 2-4%, the 13-round
+// Threefry2x64 normals and float64 fills 3-10%; one block per iteration made
+// Philox and Philox2x32 float64 normals 10-11% faster, their float64 uniforms
+// and normals and Philox2x32 uniforms 1-9%.  Left out where neither helped:
+// Threefry4x32 (8-10% slower with two blocks, as the compiler then held both
+// blocks' state, 38 -> 62 VGPRs; 15-20% slower with one), Philox and
+// Philox2x32 u32, Tyche normals, 13-round Threefry2x64 u32 / uniform.
 template <int G, int D>
-constexpr bool fast_span() {
+constexpr int fast_span() {
     if constexpr (G == G_TF2X64 || G == G_SQUARES || G == G_SQUARES64)
-        return true;
+        return 1;
     else if constexpr (G == G_TF2X64_13)
-        return D != D_U32 && D != D_UNIFORM;
+        return D != D_U32 && D != D_UNIFORM ? 1 : 0;
     else if constexpr (tyche_like(G))
-        return D != D_NORMAL && D != D_F64N;
+        return D != D_NORMAL && D != D_F64N ? 1 : 0;
+    else if constexpr (G == G_PHILOX)
+        return D == D_NORMAL || D == D_F64U || D == D_F64N ? 2 : 0;
+    else if constexpr (G == G_PHILOX2X32)
+        return D != D_U32 && D != D_F64U ? 2 : 0;
     else
-        return false;
+        return 0;
 }
 
 template <int G, int D, bool NT>

@@ -119,10 +119,10 @@ __device__ __forceinline__ void emit_block(SpanOut &o, uint64_t b, const uint32_
 }
 
 // FAST: compile in the check-free loop for spans wholly inside the range on
-// the block grid (the plain fill kernel); the batched and served kernels,
-// whose outputs are mostly off the grid, leave it out to keep their register
-// counts (34 instead of 58-59 VGPRs).
-template <int G, int D, bool NT, bool FAST = false>
+// the block grid (the plain fill kernel; 1: two blocks per iteration, 2: one);
+// the batched and served kernels, whose outputs are mostly off the grid, leave
+// it out (0) to keep their register counts (34 instead of 58-59 VGPRs).
+template <int G, int D, bool NT, int FAST = 0>
 __device__ __forceinline__ void process_span(const KeySched &ks, uint32_t ctr, char *base,
                                              uint64_t p0, uint64_t pend, uint64_t span,
                                              uint32_t unroll, uint32_t delta, uint32_t lane) {
@@ -149,7 +149,7 @@ __device__ __forceinline__ void process_span(const KeySched &ks, uint32_t ctr, c
         TycheT<G == G_TYCHE_I> st;
         st.seed(ks, (uint32_t)span * 64u + lane, ctr);
         const uint64_t tile_block = span * TYCHE_TILE_BLOCKS;
-        if (FAST && delta == 0 && tile_block * 4 >= p0 &&
+        if (FAST != 0 && delta == 0 && tile_block * 4 >= p0 &&
             (tile_block + TYCHE_TILE_BLOCKS) * 4 <= pend) {
             char *q = base + 4 * ((tile_block + lane) * 4 - p0);
             for (uint32_t k = 0; k < 64; ++k) {
@@ -176,10 +176,21 @@ __device__ __forceinline__ void process_span(const KeySched &ks, uint32_t ctr, c
         }
     } else {
         const uint64_t b0 = span * 64u * unroll;
-        if (FAST && delta == 0 && b0 * 4 >= p0 && (b0 + 64u * unroll) * 4 <= pend) {
+        if (FAST != 0 && delta == 0 && b0 * 4 >= p0 && (b0 + 64u * unroll) * 4 <= pend) {
             char *q = base + 4 * ((b0 + lane) * 4 - p0);
             uint32_t b = (uint32_t)(b0 + lane);
             uint32_t u = 0;
+            if constexpr (FAST == 2) {
+                for (; u < unroll; ++u) {
+                    uint32_t w[4];
+                    counter_block<G>(b, ctr, ks, w);
+                    convert4<D>(w);
+                    store16<NT>(q, w);
+                    q += 1024;
+                    b += 64u;
+                }
+                return;
+            }
             for (; u + 1 < unroll; u += 2) {
                 uint32_t w[4], w2[4];
                 counter_block<G>(b, ctr, ks, w);
