@@ -109,22 +109,22 @@ def roofs(gen, dist, n, ms):
 # calibration factors a 1 GiB device copy gives for each counter.  Valid only
 # for the kernel sources and launch table they were measured on: bench.py
 # reports null traffic when the hash of those sources differs.
-TRAFFIC_SRC_SHA = "02ad80091588932f"
-TRAFFIC_FACTORS = (1.9999220401636202, 1.0)  # FETCH, WRITE
+TRAFFIC_SRC_SHA = "5f246ab2cbf1f927"
+TRAFFIC_FACTORS = (1.9999227553638532, 1.0)  # FETCH, WRITE
 TRAFFIC_KIB = {
-    (0, 0): (79.375, 4194304.0), (0, 1): (45.5, 4194651.125), (0, 2): (84.1875, 4194339.625), (0, 3): (50.0, 4194304.0),
-    (0, 4): (75.0, 4194320.84375), (1, 0): (55.875, 4194318.25), (1, 1): (60.5, 4194305.25), (1, 2): (72.125, 4194304.0),
-    (1, 3): (53.5625, 4194316.15625), (1, 4): (76.0, 4194305.09375), (2, 0): (38.0, 4194314.375), (2, 1): (42.0, 4194332.375),
-    (2, 2): (81.0, 4194304.0), (2, 3): (45.5, 4194318.5), (2, 4): (59.0, 4194304.0), (3, 0): (37.5, 4194336.5),
-    (3, 1): (39.0, 4194304.0), (3, 2): (76.125, 4194318.25), (3, 3): (39.0, 4197170.75), (3, 4): (49.0, 4194319.03125),
-    (4, 0): (25.75, 4194304.0), (4, 1): (32.5625, 4194304.0), (4, 2): (42.875, 4194304.0), (4, 3): (38.21875, 4194304.0),
-    (4, 4): (40.046875, 4194314.59375), (5, 0): (51.0, 4195648.65625), (5, 1): (43.0, 4195093.40625), (5, 2): (58.0, 4194329.4375),
-    (5, 3): (52.5, 4196602.84375), (5, 4): (72.5, 4194312.78125), (6, 0): (44.5, 4194304.0), (6, 1): (52.5, 4195981.875),
-    (6, 2): (53.5, 4194327.8125), (6, 3): (40.0, 4197866.53125), (6, 4): (71.0, 4194311.5625), (7, 0): (31.171875, 4194304.0),
-    (7, 1): (31.703125, 4194304.0), (7, 2): (29.015625, 4194543.125), (7, 3): (29.53125, 4194304.0), (7, 4): (43.109375, 4194313.59375),
-    (8, 0): (34.0, 4197338.0625), (8, 1): (27.5, 4194304.0), (8, 2): (50.0, 4194368.15625), (8, 3): (35.5, 4196393.34375),
-    (8, 4): (63.0, 4194316.34375), (9, 0): (43.0, 4194304.0), (9, 1): (52.0, 4194304.0), (9, 2): (61.5, 4194313.84375),
-    (9, 3): (46.0, 4194304.0), (9, 4): (69.0, 4194325.59375),
+    (0, 0): (80.4375, 4194304.0), (0, 1): (45.4375, 4195201.5), (0, 2): (63.4375, 4194307.75), (0, 3): (27.5, 4194304.0),
+    (0, 4): (40.0, 4194320.75), (1, 0): (41.375, 4194319.875), (1, 1): (63.5625, 4194322.375), (1, 2): (65.375, 4194304.0),
+    (1, 3): (56.0625, 4194325.9375), (1, 4): (73.0, 4194305.15625), (2, 0): (44.0, 4194308.5), (2, 1): (47.0, 4194363.875),
+    (2, 2): (87.375, 4194304.0), (2, 3): (42.5, 4194322.875), (2, 4): (82.390625, 4194304.0), (3, 0): (37.5, 4194353.875),
+    (3, 1): (31.0, 4195754.75), (3, 2): (72.5, 4194320.75), (3, 3): (36.0, 4198136.21875), (3, 4): (64.0, 4194321.65625),
+    (4, 0): (33.125, 4194304.0), (4, 1): (27.1875, 4194304.0), (4, 2): (37.8125, 4194311.25), (4, 3): (33.765625, 4194304.0),
+    (4, 4): (43.078125, 4194316.75), (5, 0): (43.5, 4195897.0), (5, 1): (45.5, 4195480.15625), (5, 2): (63.0, 4194332.5),
+    (5, 3): (53.0, 4196126.71875), (5, 4): (70.0, 4194313.25), (6, 0): (52.0, 4194304.0), (6, 1): (53.5, 4197727.9375),
+    (6, 2): (42.5, 4194329.65625), (6, 3): (37.0, 4197525.40625), (6, 4): (66.0, 4194310.6875), (7, 0): (31.421875, 4194304.0),
+    (7, 1): (32.53125, 4194304.0), (7, 2): (36.53125, 4194354.1875), (7, 3): (31.65625, 4194304.0), (7, 4): (37.09375, 4194315.34375),
+    (8, 0): (34.0, 4197164.53125), (8, 1): (35.578125, 4194304.0), (8, 2): (45.0, 4194361.6875), (8, 3): (35.5, 4197798.1875),
+    (8, 4): (54.5, 4194315.8125), (9, 0): (51.0, 4194304.0), (9, 1): (19.0, 4194304.0), (9, 2): (26.0, 4194342.28125),
+    (9, 3): (51.0, 4194304.0), (9, 4): (42.5, 4194315.40625),
 }
 
 
