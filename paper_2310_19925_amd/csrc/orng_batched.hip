@@ -248,35 +248,6 @@ static void *batched_kernel(const BatchShape &s, bool f64n, bool rng) {
     return rng ? batched_kernel_v<false, true>(s) : batched_kernel_v<false, false>(s);
 }
 
-int validate_request(const orng_req_t &r) {
-    if (r.gen > ORNG_PHILOX2X32 || r.dist > ORNG_I32_RANGE || r.flags != 0) return ORNG_EINVAL;
-    if (!seed_ok((int)r.gen, r.seed)) return ORNG_EINVAL;
-    if (r.dist == ORNG_I32_RANGE && r.lo >= r.hi) return ORNG_EINVAL;
-    const uint64_t lim = sample_limit((int)r.dist);
-    if (r.offset > lim || r.n > lim - r.offset) return ORNG_ERANGE;
-    if (r.n == 0) return ORNG_OK;
-    if (!r.out || (reinterpret_cast<uintptr_t>(r.out) & (bytes_per_sample((int)r.dist) - 1)))
-        return ORNG_EINVAL;
-    return ORNG_OK;
-}
-
-// Kernel-side bounds of an integer-range request: lo's bits and r = hi - lo.
-void range_bounds(const orng_req_t &r, uint32_t *lo, uint32_t *rr) {
-    const bool on = r.dist == ORNG_I32_RANGE;
-    *lo = on ? (uint32_t)r.lo : 0u;
-    *rr = on ? (uint32_t)((int64_t)r.hi - (int64_t)r.lo) : 0u;
-}
-
-// (address of out in words - first position) mod 4: the alignment class of a
-// request's output against its block grid, in words; for integer ranges,
-// whose output samples are one word each, against its sample grid.
-uint32_t output_delta(const orng_req_t &r, const void *out) {
-    const uint64_t addr_words = reinterpret_cast<uintptr_t>(out) / 4;
-    const uint64_t first =
-        r.dist == ORNG_I32_RANGE ? r.offset : r.offset * words_per_sample((int)r.dist);
-    return (uint32_t)((addr_words - first) & 3u);
-}
-
 // Tile decomposition of one request: spans of `unroll` blocks per lane,
 // W spans per tile.
 // (Span and tile sizes are powers of two at every built-in launch shape; the
@@ -458,14 +429,27 @@ int fill_batched(const orng_req_t *reqs, size_t nreq, hipStream_t stream) {
     uint32_t unroll_of[NGEN][NREQDIST];  // one table lookup per pair, not per request
     unroll_table(unroll_of);
 
-    // per-request first span and tile count, in arrays kept by the calling
-    // thread across calls (fresh ones cost a page fault per 4 KiB on first touch)
+    // per-request first span and tile count: for batches of up to 2^20
+    // requests in arrays kept by the calling thread across calls (fresh ones
+    // cost a page fault per 4 KiB on first touch; at most 16 MiB per thread),
+    // for larger ones in arrays of this call
+    constexpr size_t KEEP = size_t(1) << 20;
     static thread_local std::vector<uint64_t> t_fspan, t_cnt;
-    if (t_fspan.size() < nreq) {
-        t_fspan.resize(nreq);
-        t_cnt.resize(nreq);
+    std::vector<uint64_t> big_fspan, big_cnt;
+    uint64_t *fspan, *cnt;
+    if (nreq <= KEEP) {
+        if (t_fspan.size() < nreq) {
+            t_fspan.resize(nreq);
+            t_cnt.resize(nreq);
+        }
+        fspan = t_fspan.data();
+        cnt = t_cnt.data();
+    } else {
+        big_fspan.resize(nreq);
+        big_cnt.resize(nreq);
+        fspan = big_fspan.data();
+        cnt = big_cnt.data();
     }
-    uint64_t *fspan = t_fspan.data(), *cnt = t_cnt.data();
     std::vector<uint64_t> range_tiles(rg.T + 1, 0);
     rg.run([&](size_t t, size_t a, size_t b) {
         uint64_t sum = 0;

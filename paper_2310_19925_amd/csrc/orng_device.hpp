@@ -20,21 +20,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "orng_host.hpp"
+
 namespace orng {
-
-enum GenId : int { G_PHILOX = 0, G_TF4X32 = 1, G_TF2X64 = 2, G_SQUARES = 3, G_TYCHE = 4,
-                   G_TF4X32_13 = 5, G_TF2X64_13 = 6, G_TYCHE_I = 7, G_SQUARES64 = 8,
-                   G_PHILOX2X32 = 9 };
-enum DistId : int { D_U32 = 0, D_UNIFORM = 1, D_NORMAL = 2, D_F64U = 3, D_F64N = 4,
-                    D_I32R = 5 };
-// NDIST: distributions of the fill kernels and launch tables; request records
-// (batched and served) also take D_I32R, integers in [lo, hi), whose bounds
-// they carry.
-constexpr int NGEN = 10, NDIST = 5, NREQDIST = 6;
-
-// Tyche and Tyche-i share the tile layout (no random access within a
-// substream); every other generator is counter-based with 4-word blocks.
-__host__ __device__ constexpr bool tyche_like(int g) { return g == G_TYCHE || g == G_TYCHE_I; }
 
 // Per-launch key material, uniform across the grid.
 struct KeySched {
@@ -379,8 +367,6 @@ __host__ __device__ inline KeySched make_keysched(uint64_t seed) {
     return k;
 }
 
-constexpr uint32_t TYCHE_TILE_WORDS = 16384;
-constexpr uint32_t TYCHE_TILE_BLOCKS = 4096;
 
 // ---------------------------------------------------------------------------
 // float32 conversions.

@@ -10,25 +10,6 @@
 
 namespace orng {
 
-constexpr uint64_t PERIOD = 1ull << 32;
-
-// Stream words per sample: a float64 sample is made from the word pair
-// (2p, 2p+1) (a float64 normal pair from the block 4m..4m+3), and so is an
-// integer in [lo, hi); every other distribution from one word.  The public
-// calls take offsets and counts in samples and convert them to words
-// (positions) once; below that, every launcher and kernel works in words.
-inline uint64_t words_per_sample(int dist) { return dist >= D_F64U ? 2 : 1; }
-inline uint64_t sample_limit(int dist) { return PERIOD / words_per_sample(dist); }
-// Output bytes per sample: 8 for the float64 distributions, 4 otherwise.
-inline uint64_t bytes_per_sample(int dist) { return dist == D_F64U || dist == D_F64N ? 8 : 4; }
-// The launch-table row a request's distribution takes in the batched and
-// served paths: integers in [lo, hi) read the same two words per sample as
-// float64 uniforms and use that row.
-inline int shape_dist(int dist) { return dist == D_I32R ? D_F64U : dist; }
-
-// Philox2x32-10 keys with one 32-bit word: its seeds must be below 2^32.
-inline bool seed_ok(int gen, uint64_t seed) { return gen != G_PHILOX2X32 || seed <= 0xFFFFFFFFull; }
-
 // Launch knobs.  0 means "choose automatically".
 struct LaunchCfg {
     uint32_t wg_size;   // threads per workgroup (multiple of 64, <= 512)

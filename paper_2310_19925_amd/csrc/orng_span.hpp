@@ -392,9 +392,5 @@ __device__ __forceinline__ void process_span_any(int gen, int dist, const KeySch
 #undef ORNG_RCASE
 }
 
-// Blocks per span for a generator.
-__host__ __device__ inline uint64_t span_blocks(int gen, uint32_t unroll) {
-    return tyche_like(gen) ? (uint64_t)TYCHE_TILE_BLOCKS : 64ull * unroll;
-}
 
 }  // namespace orng

@@ -7,7 +7,11 @@
   outputs must equal those of the ordinary oracle build byte for byte;
 - the server's arena allocator (host-only header): 200,000 random
   allocations and releases checked against a granule-map model (first fit,
-  bounds, no overlap, used and peak bytes, coalescing back to one range).
+  bounds, no overlap, used and peak bytes, coalescing back to one range);
+- the request-record checks of the batched and served paths (host-only
+  header): 200,000 requests drawn on and around every boundary, each
+  compared with the documented rules (return code, integer-range bounds,
+  output alignment class).
 """
 import os
 import shutil
@@ -83,3 +87,51 @@ def test_oracle_under_sanitizers_matches_the_plain_build(O, tmp_path):
 def test_arena_allocator_under_sanitizers(tmp_path):
     exe = _build(tmp_path, "arena_check", [os.path.join(HERE, "arena_check.cc")])
     assert _run([exe, "200000"]).strip() == "OK 200000 steps"
+
+
+def _request_model(gen, dist, flags, seed, offset, n, addr, lo, hi):
+    """The request checks the fill calls document: (return code, lo bits,
+    hi - lo mod 2^32, output alignment class in words)."""
+    OK, EINVAL, ERANGE = 0, -1, -2
+    lo = lo - (1 << 32) if lo >= 1 << 31 else lo
+    hi = hi - (1 << 32) if hi >= 1 << 31 else hi
+    rng = dist == 5
+    bounds = ((lo & 0xFFFFFFFF, (hi - lo) & 0xFFFFFFFF) if rng else (0, 0))
+    if gen > 9 or dist > 5 or flags != 0:
+        return (EINVAL,) + bounds + (0,)
+    if gen == 9 and seed >= 1 << 32:        # Philox2x32-10: one 32-bit key word
+        return (EINVAL,) + bounds + (0,)
+    if rng and lo >= hi:
+        return (EINVAL,) + bounds + (0,)
+    words = 2 if dist >= 3 else 1           # float64 and integer ranges read word pairs
+    limit = (1 << 32) // words
+    if offset > limit or n > limit - offset:
+        return (ERANGE,) + bounds + (0,)
+    if n == 0:
+        return (OK,) + bounds + (0,)
+    size = 8 if dist in (3, 4) else 4
+    if addr == 0 or addr % size:
+        return (EINVAL,) + bounds + (0,)
+    first = offset if rng else offset * words
+    return (OK,) + bounds + ((addr // 4 - first) % 4,)
+
+
+def test_request_checks_under_sanitizers(tmp_path):
+    exe = _build(tmp_path, "request_check", [os.path.join(HERE, "request_check.cc")])
+    n = 200000
+    out = tmp_path / "rows.bin"
+    assert _run([exe, str(n), str(out)]).strip() == "OK %d requests" % n
+    rows = np.fromfile(str(out), dtype=np.uint64).reshape(n, 13)
+    codes, aligned = {}, [0] * 4
+    for row in rows.tolist():
+        gen, dist, flags, seed, _ctr, offset, cnt, addr, lo, hi, rc, lob, packed = row
+        rc = rc - (1 << 64) if rc >= 1 << 63 else rc
+        got = (rc, lob, packed >> 32, packed & 0xFFFFFFFF)
+        want = _request_model(gen, dist, flags, seed, offset, cnt, addr, lo, hi)
+        assert got == want, (row, got, want)
+        codes[rc] = codes.get(rc, 0) + 1
+        if rc == 0 and cnt > 0:
+            aligned[got[3]] += 1
+    # the draw reaches every outcome often, and every alignment class
+    assert min(codes.get(c, 0) for c in (0, -1, -2)) > 5000, codes
+    assert min(aligned) > 1000, aligned
