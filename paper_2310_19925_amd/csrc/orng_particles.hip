@@ -7,11 +7,26 @@
 //   out[(t * n_particles + p) * draws + k] = word k of stream (seed0 + p, ctr0 + t)
 // Word k of a stream is the same word orng_fill returns at position k.
 //
-// One lane per particle forms its key schedule once (it depends only on the
-// seed) and runs a chunk of iterations; the wave's micro-streams of an
-// iteration are contiguous in the output and are stored through LDS.
-// Iterations are cut into chunks so that a few thousand particles still fill
-// the device with many workgroups.
+// Two schedules:
+// - flat (Philox4x32, both Threefry4x32 forms and Squares64; micro-streams of
+//   at most four words, at least 1024 particles, a 16-byte aligned output):
+//   workgroup w makes the 1024 (iteration, particle) slots 1024 w .. 1024 w +
+//   1023 of the output order, four per thread, each with its own key
+//   schedule, and stores its 4096 * draws contiguous bytes in 16-byte chunks.
+//   Every workgroup's share of the output is a whole number of 4 KiB pieces
+//   at 4 KiB offsets from the output's start (on MI355X, where consecutive
+//   workgroups run on different XCDs, a pure-store probe wrote such pieces at
+//   6.9 TB/s and 3 KiB pieces, the lane schedule's share, at 5.6 TB/s).
+//   Measured against the lane schedule on 16,000 x 3 x 22,369 words, the
+//   flat one is 17-18% faster for the Threefry4x32 forms and 2% for Philox4x32
+//   and Squares64, and 2-7% slower for the other generators, which keep the
+//   lane schedule: there the key schedule per slot, or Tyche's seeding, costs
+//   more than the store pattern gains.
+// - lane per particle (any other shape): a lane forms its key schedule once
+//   (it depends only on the seed) and runs a chunk of iterations; the wave's
+//   micro-streams of an iteration are contiguous in the output and are stored
+//   through LDS.  Iterations are cut into chunks so that a few thousand
+//   particles still fill the device with many workgroups.
 #include "../../include/orng.h"
 #include "orng_device.hpp"
 #include "orng_internal.hpp"
@@ -86,9 +101,87 @@ __global__ __launch_bounds__(256) void k_particles(PartArgs a) {
     }
 }
 
+struct FlatArgs {
+    uint32_t *out;          // 16-byte aligned
+    uint64_t seed0;
+    uint32_t n_particles;   // >= FLAT_SLOTS
+    uint32_t ctr0;
+    uint32_t n_full;        // workgroups with FLAT_SLOTS slots; one more holds the tail
+    uint32_t tail;          // slots of the last workgroup when n_iters * n_particles
+                            // is not a multiple of FLAT_SLOTS (0 otherwise)
+};
+
+constexpr uint32_t FLAT_SLOTS = 1024;  // slots per workgroup (256 threads, four each)
+
+// Slot j of a workgroup whose first slot is (iteration t0, particle p0):
+// its DT words into the workgroup's LDS staging area.
+template <int G, int DT>
+__device__ __forceinline__ void flat_slot(const FlatArgs &a, uint32_t t0, uint32_t p0, uint32_t j,
+                                          uint32_t *lds) {
+    // p0 < n_particles and j < 1024 <= n_particles: at most one wrap
+    uint32_t p = p0 + j, t = t0;
+    if (p >= a.n_particles) { p -= a.n_particles; ++t; }
+    const uint32_t ctr = a.ctr0 + t;
+    const KeySched ks = make_keysched(a.seed0 + p);
+    uint32_t w[4];
+    counter_block<G>(0, ctr, ks, w);
+#pragma unroll
+    for (int k = 0; k < DT; ++k) lds[j * DT + k] = w[k];
+}
+
+template <int G, int DT>
+__global__ __launch_bounds__(256) void k_particles_flat(FlatArgs a) {
+    static_assert(DT >= 1 && DT <= 4, "one block of four words per slot");
+    static_assert(!tyche_like(G), "counter-based generators only");
+    __shared__ __align__(16) uint32_t lds[FLAT_SLOTS * DT];
+    const uint64_t s0 = (uint64_t)blockIdx.x * FLAT_SLOTS;
+    // the slot count from two 32-bit kernel arguments: a clamp of the 64-bit
+    // remainder (n_slots - s0 against FLAT_SLOTS) compiled to a select on a
+    // stale scalar condition code with this toolchain and gave the last
+    // workgroup FLAT_SLOTS slots
+    const uint32_t ns = blockIdx.x < a.n_full ? FLAT_SLOTS : a.tail;
+    // s0 = t0 * n_particles + p0 (uniform: one scalar division per workgroup)
+    const uint64_t t0 = s0 / a.n_particles;
+    const uint32_t p0 = (uint32_t)(s0 - t0 * a.n_particles);
+    if (ns == FLAT_SLOTS) {
+        // every workgroup but the last: the four slots of a thread are
+        // independent and unconditional, so their rounds interleave
+#pragma unroll
+        for (uint32_t q = 0; q < FLAT_SLOTS / 256; ++q)
+            flat_slot<G, DT>(a, (uint32_t)t0, p0, threadIdx.x + 256u * q, lds);
+    } else {
+        for (uint32_t j = threadIdx.x; j < ns; j += 256)
+            flat_slot<G, DT>(a, (uint32_t)t0, p0, j, lds);
+    }
+    __syncthreads();
+    const uint32_t nw = ns * DT;
+    uint32_t *o = a.out + s0 * DT;
+#pragma unroll
+    for (uint32_t r = 0; r < DT; ++r) {
+        const uint32_t c = 4u * (threadIdx.x + 256u * r);  // first word of this chunk
+        if (c + 4 <= nw) {
+            *reinterpret_cast<uint4 *>(o + c) = *reinterpret_cast<const uint4 *>(lds + c);
+        } else {
+            for (uint32_t k = c; k < nw; ++k) o[k] = lds[k];  // the last workgroup's tail
+        }
+    }
+}
+
 }  // namespace orng
 
 using namespace orng;
+
+// The flat schedule's kernel for a generator that takes it, else nullptr.
+template <int DT>
+static void *flat_kernel(int gen) {
+    switch (gen) {
+    case G_PHILOX: return reinterpret_cast<void *>(&k_particles_flat<G_PHILOX, DT>);
+    case G_TF4X32: return reinterpret_cast<void *>(&k_particles_flat<G_TF4X32, DT>);
+    case G_TF4X32_13: return reinterpret_cast<void *>(&k_particles_flat<G_TF4X32_13, DT>);
+    case G_SQUARES64: return reinterpret_cast<void *>(&k_particles_flat<G_SQUARES64, DT>);
+    default: return nullptr;
+    }
+}
 
 extern "C" int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particles,
                                      uint32_t draws, uint32_t ctr0, uint32_t n_iters,
@@ -100,6 +193,27 @@ extern "C" int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particl
     if (n_particles && !seed_ok(gen, seed0 + (n_particles - 1))) return ORNG_ERANGE;
     if (!n_particles || !n_iters) return ORNG_OK;
     if (!d_out || (reinterpret_cast<uintptr_t>(d_out) & 3u)) return ORNG_EINVAL;
+    const uint64_t n_slots = (uint64_t)n_particles * n_iters;
+    const uint64_t flat_grid = (n_slots + FLAT_SLOTS - 1) / FLAT_SLOTS;
+    void *flat = draws == 1 ? flat_kernel<1>(gen)
+               : draws == 2 ? flat_kernel<2>(gen)
+               : draws == 3 ? flat_kernel<3>(gen)
+               : draws == 4 ? flat_kernel<4>(gen) : nullptr;
+    if (flat && n_particles >= FLAT_SLOTS && flat_grid <= 0x7FFFFFFFull &&
+        (reinterpret_cast<uintptr_t>(d_out) & 15u) == 0) {
+        FlatArgs f;
+        f.out = static_cast<uint32_t *>(d_out);
+        f.seed0 = seed0;
+        f.n_particles = n_particles;
+        f.n_full = (uint32_t)(n_slots / FLAT_SLOTS);
+        f.tail = (uint32_t)(n_slots % FLAT_SLOTS);
+        f.ctr0 = ctr0;
+        void *args[] = {&f};
+        const hipError_t e = hipLaunchKernel(flat, dim3((uint32_t)flat_grid), dim3(256), args, 0,
+                                             static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; }
+        return ORNG_OK;
+    }
     PartArgs a;
     a.out = static_cast<uint32_t *>(d_out);
     a.seed0 = seed0;
