@@ -363,3 +363,39 @@ def test_batched_ranges_with_float64_normals(R, O):
             assert np.all(host[~written] == 0xFFFFFFFF)  # nothing outside the outputs
     finally:
         R.orng_reset_launch()
+
+
+def test_batched_more_requests_than_kept_arrays(R, O):
+    """A batch of 1,200,000 requests (more than the 2^20 whose per-request
+    tiling arrays the calling thread keeps between calls, so this call uses
+    arrays of its own), then a small batch that uses the kept arrays, then the
+    large one again: Philox4x32 u32 and Squares64 f32 uniform requests of
+    three words each, packed back to back, request i on stream counter i."""
+    m, seed = 1_200_000, 0x2310_19925
+    gen = np.where(np.arange(m) % 2 == 0, 0, 8)
+    dist = np.where(gen == 0, 0, 1)
+    buf = torch.full((3 * m + 16,), -1, dtype=torch.int32, device="cuda")
+    reqs = R.make_requests(gen, dist, seed, np.arange(m), 5, 3,
+                           buf.data_ptr() + 12 * np.arange(m, dtype=np.uint64))
+    want = np.empty((m, 3), np.uint32)
+    want[0::2] = O.fill_multi(0, 0, seed, 0, m, 5, 3).view(np.uint32).reshape(m, 3)[0::2]
+    want[1::2] = O.fill_multi(8, 1, seed, 0, m, 5, 3).view(np.uint32).reshape(m, 3)[1::2]
+    small = torch.full((1000,), -1, dtype=torch.int32, device="cuda")
+    sreq = R.make_requests(3, 0, 77, np.arange(10), 0, 100,
+                           small.data_ptr() + 400 * np.arange(10, dtype=np.uint64))
+    for rnd in range(2):
+        buf.fill_(-1)
+        R.orng_fill_batched(reqs)
+        torch.cuda.synchronize()
+        host = buf.cpu().numpy().view(np.uint32)
+        assert np.all(host[3 * m:] == 0xFFFFFFFF), rnd
+        bad = np.flatnonzero((host[:3 * m].reshape(m, 3) != want).any(axis=1))
+        assert bad.size == 0, (rnd, bad.size, bad[:5])
+        if rnd == 0:
+            R.orng_fill_batched(sreq)
+            torch.cuda.synchronize()
+            assert np.array_equal(small.cpu().numpy().view(np.uint32).reshape(10, 100),
+                                  O.fill_multi(3, 0, 77, 0, 10, 0, 100).view(np.uint32)
+                                  .reshape(10, 100))
+    del buf
+    torch.cuda.empty_cache()
