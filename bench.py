@@ -441,14 +441,15 @@ def bench_bd2(orng, inputs, stream, dev, per_step_too=True):
 # VALU slots per 3-word micro-stream (one stream per particle and iteration):
 # one counter block for Philox/Threefry (3 of its 4 words used); three
 # Squares words plus the y product; Tyche seeds an instance (20 MIX) and runs
-# 4 more (12 slots per MIX); the 13-round Threefry blocks; Tyche-i as Tyche;
+# 3 more for its 3 words (12 slots per MIX); the 13-round Threefry blocks;
+# Tyche-i as Tyche;
 # Squares64 two calls (5 rounds of 3 slots, the 64-bit adds and the XOR);
 # Philox2x32 two two-word blocks.  The generators that run this shape with one
 # key schedule per micro-stream (the flat schedule) also pay for it: Philox's
 # 18 round-key additions, Threefry4x32's parity word, and Squares64's key
 # (one SplitMix64 step, about 20 slots).
-PART_SLOTS_3 = {0: 38 + 18, 1: 128 + 1, 2: 109, 3: 3 + 3 * 13, 4: 24 * 12, 5: 80 + 1, 6: 70,
-                7: 24 * 12, 8: 3 + 2 * 18 + 20, 9: 40}
+PART_SLOTS_3 = {0: 38 + 18, 1: 128 + 1, 2: 109, 3: 3 + 3 * 13, 4: 23 * 12, 5: 80 + 1, 6: 70,
+                7: 23 * 12, 8: 3 + 2 * 18 + 20, 9: 40}
 
 
 def bench_particles(orng, inputs, stream, dev):
