@@ -349,7 +349,8 @@ typedef struct {
     uint64_t arena_bytes;   /* HBM budget for outputs in flight (> 0) */
     uint32_t max_slots;     /* requests resident on the device at once (0: 4096) */
     uint32_t flags;         /* reserved, 0 */
-    uint64_t step_words;    /* most words generated per device step (0: automatic) */
+    uint64_t step_words;    /* most words generated per device step (0: automatic, 2^30;
+                               at most 2^34) */
 } orng_serve_cfg_t;
 
 typedef struct {
@@ -374,7 +375,8 @@ typedef struct {
     double first_submit_to_last_done_s;
 } orng_serve_stats_t;
 
-/* Create a server.  Errors: EINVAL (cfg), EHIP (stream/arena allocation). */
+/* Create a server.  Errors: EINVAL (cfg: arena_bytes < 256, a misaligned arena,
+   flags != 0, step_words > 2^34), EHIP (stream/arena allocation). */
 int orng_serve_create(const orng_serve_cfg_t *cfg, orng_server_t **srv);
 /* Queue a request; never blocks on the device.  req->out == NULL asks the
    server for an arena output (released by orng_serve_release); otherwise the

@@ -217,8 +217,11 @@ static BatchShape batch_shape(int gen, int dist, uint64_t tiles) {
     s.chunk = tu.b_chunk ? tu.b_chunk : 1;
     s.nt = false;
     const uint64_t wpg = s.wg / 64;
-    // b_wgs_per_cu == 0 selects the static one-wave-per-tile schedule
-    s.persistent = tu.b_wgs_per_cu != 0 || cfg.max_wgs != 0;
+    // b_wgs_per_cu == 0 selects the static one-workgroup-per-tile schedule,
+    // unless its grid would pass the dispatch limit of 2^32 work-items per
+    // dimension (batches of 2^23 tiles and more, 16 GiB or more of output)
+    const bool static_fits = (bucket(tiles) + XCDS - 1) / XCDS * XCDS <= max_wgs_1d(s.wg);
+    s.persistent = tu.b_wgs_per_cu != 0 || cfg.max_wgs != 0 || !static_fits;
     if (s.persistent) {
         uint64_t grid = (uint64_t)device_cu_count() * (tu.b_wgs_per_cu ? tu.b_wgs_per_cu : 4);
         if (cfg.max_wgs) grid = cfg.max_wgs;

@@ -33,8 +33,9 @@ struct Bd2Args {
 };
 
 __global__ __launch_bounds__(256) void k_bd2(Bd2Args a) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+    const uint64_t i64 = (uint64_t)flat_block() * blockDim.x + threadIdx.x;
+    if (i64 >= a.n) return;
+    const uint32_t i = (uint32_t)i64;
     const uint64_t pid = a.pid0 + i;
     const uint32_t klo = (uint32_t)pid, khi = (uint32_t)(pid >> 32);
     double pos[2] = {a.x[i], a.y[i]}, vel[2] = {a.vx[i], a.vy[i]};
@@ -79,12 +80,12 @@ extern "C" int orng_bd2(uint64_t pid0, uint32_t n, uint32_t step0, uint32_t n_st
     a.decay = 1.0 - gamma_over_m * dt;
     a.kick = 2.0 * std::sqrt(dt);
     const uint32_t per = steps_per_launch ? steps_per_launch : n_steps;
-    const uint32_t grid = (n + 255) / 256;
+    const Grid2 grid = grid_2d(blocks_for(n, 256));
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (uint32_t done = 0; done < n_steps; done += std::min(per, n_steps - done)) {
         a.step0 = step0 + done;
         a.n_steps = std::min(per, n_steps - done);
-        hipLaunchKernelGGL(k_bd2, dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_bd2, dim3(grid.x, grid.y), dim3(256), 0, s, a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; }
     }

@@ -24,6 +24,11 @@
 
 namespace orng {
 
+// Linear workgroup id of a grid launched as grid_2d(blocks) (x fastest).
+__device__ __forceinline__ uint32_t flat_block() {
+    return blockIdx.y * gridDim.x + blockIdx.x;
+}
+
 // Per-launch key material, uniform across the grid.
 struct KeySched {
     uint32_t k[10][2];   // Philox round keys (key bumped by the Weyl pair)

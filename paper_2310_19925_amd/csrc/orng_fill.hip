@@ -207,6 +207,7 @@ hipError_t launch_fill(int gen, int dist, uint64_t seed, uint32_t ctr0, uint32_t
     uint64_t grid = (a.total_spans + wpg - 1) / wpg;
     const uint64_t cap = cfg.max_wgs ? cfg.max_wgs : (tu.max_wgs ? tu.max_wgs : (1ull << 30));
     if (grid > cap) grid = cap;
+    if (grid > max_wgs_1d(wg)) grid = max_wgs_1d(wg);  // spans are grid-strided
     void *args[] = {&a};
     return hipLaunchKernel(pick_kernel(gen, dist, false, nt), dim3((uint32_t)grid), dim3(wg), args,
                            0, s);

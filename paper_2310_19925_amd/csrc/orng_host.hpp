@@ -47,6 +47,40 @@ inline int shape_dist(int dist) { return dist == D_I32R ? D_F64U : dist; }
 // Philox2x32-10 keys with one 32-bit word: its seeds must be below 2^32.
 inline bool seed_ok(int gen, uint64_t seed) { return gen != G_PHILOX2X32 || seed <= 0xFFFFFFFFull; }
 
+// Workgroups of `wg` threads that cover n items, rounded up in 64 bits so that
+// counts up to 2^32 - 1 do not wrap.
+constexpr uint32_t blocks_for(uint32_t n, uint32_t wg) {
+    return (uint32_t)(((uint64_t)n + wg - 1) / wg);
+}
+static_assert(blocks_for(0xFFFFFFFFu, 256) == 1u << 24 && blocks_for(257, 256) == 2 &&
+                  blocks_for(0, 64) == 0,
+              "workgroup counts round up without wrapping");
+
+// A dispatch holds its grid size per dimension in work-items, as a 32-bit
+// count: one dimension takes at most max_wgs_1d(wg) workgroups of wg threads.
+constexpr uint32_t max_wgs_1d(uint32_t wg) { return (uint32_t)(0xFFFFFFFFull / wg); }
+
+// `blocks` workgroups as a 2-D grid (x fastest, so the linear workgroup id
+// y * x_dim + x counts them in dispatch order; it stays below 2^32 for
+// blocks < 2^32 - 2^16): one row up to 2^16 workgroups, then rows of at most
+// 2^16.  x * y >= blocks, with fewer than y workgroups beyond `blocks`; the
+// kernels return from those.
+struct Grid2 {
+    uint32_t x, y;
+};
+constexpr Grid2 grid_2d(uint64_t blocks) {
+    const uint64_t row = 65536;
+    return blocks <= row ? Grid2{(uint32_t)blocks, 1u}
+                         : Grid2{(uint32_t)((blocks + (blocks + row - 1) / row - 1) /
+                                            ((blocks + row - 1) / row)),
+                                 (uint32_t)((blocks + row - 1) / row)};
+}
+static_assert(grid_2d(100).x == 100 && grid_2d(100).y == 1, "one row");
+static_assert((uint64_t)grid_2d((1ull << 32) - 1).x * grid_2d((1ull << 32) - 1).y >=
+                      (1ull << 32) - 1 &&
+                  grid_2d((1ull << 32) - 1).x <= 65536,
+              "rows cover every workgroup");
+
 // Blocks (of four words) per span for a generator: 64 per unit of `unroll`,
 // or one Tyche tile.
 constexpr uint64_t span_blocks(int gen, uint32_t unroll) {

@@ -41,6 +41,7 @@ struct PartArgs {
     uint32_t n_particles, draws, ctr0, n_iters;
     uint32_t xblocks;       // workgroups across the particles
     uint32_t iters_per_wg;  // iterations per workgroup
+    uint32_t n_wgs;         // workgroups with work (the grid may hold a few more)
 };
 
 // A wave's 64 particles own 64 * draws consecutive output words per
@@ -54,7 +55,9 @@ struct PartArgs {
 template <int G, int DT>
 __global__ __launch_bounds__(256) void k_particles(PartArgs a) {
     __shared__ uint32_t lds[256 * 16];
-    const uint32_t xb = blockIdx.x % a.xblocks, tb = blockIdx.x / a.xblocks;
+    const uint32_t b = flat_block();
+    if (b >= a.n_wgs) return;  // beyond the last workgroup of a two-row grid
+    const uint32_t xb = b % a.xblocks, tb = b / a.xblocks;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t pw0 = xb * 256 + wave * 64;  // first particle of the wave
     if (pw0 >= a.n_particles) return;           // whole wave past the end
@@ -134,12 +137,14 @@ __global__ __launch_bounds__(256) void k_particles_flat(FlatArgs a) {
     static_assert(DT >= 1 && DT <= 4, "one block of four words per slot");
     static_assert(!tyche_like(G), "counter-based generators only");
     __shared__ __align__(16) uint32_t lds[FLAT_SLOTS * DT];
-    const uint64_t s0 = (uint64_t)blockIdx.x * FLAT_SLOTS;
+    const uint32_t b = flat_block();
+    if (b > a.n_full || (b == a.n_full && a.tail == 0)) return;  // past the last workgroup
+    const uint64_t s0 = (uint64_t)b * FLAT_SLOTS;
     // the slot count from two 32-bit kernel arguments: a clamp of the 64-bit
     // remainder (n_slots - s0 against FLAT_SLOTS) compiled to a select on a
     // stale scalar condition code with this toolchain and gave the last
     // workgroup FLAT_SLOTS slots
-    const uint32_t ns = blockIdx.x < a.n_full ? FLAT_SLOTS : a.tail;
+    const uint32_t ns = b < a.n_full ? FLAT_SLOTS : a.tail;
     // s0 = t0 * n_particles + p0 (uniform: one scalar division per workgroup)
     const uint64_t t0 = s0 / a.n_particles;
     const uint32_t p0 = (uint32_t)(s0 - t0 * a.n_particles);
@@ -199,7 +204,10 @@ extern "C" int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particl
                : draws == 2 ? flat_kernel<2>(gen)
                : draws == 3 ? flat_kernel<3>(gen)
                : draws == 4 ? flat_kernel<4>(gen) : nullptr;
-    if (flat && n_particles >= FLAT_SLOTS && flat_grid <= 0x7FFFFFFFull &&
+    // (the flat kernel's p0 + j stays below 2^32 only when n_particles does not
+    // come within FLAT_SLOTS of it)
+    if (flat && n_particles >= FLAT_SLOTS && n_particles <= 0xFFFFFFFFu - FLAT_SLOTS &&
+        flat_grid <= 0xFFFF0000ull &&
         (reinterpret_cast<uintptr_t>(d_out) & 15u) == 0) {
         FlatArgs f;
         f.out = static_cast<uint32_t *>(d_out);
@@ -209,7 +217,8 @@ extern "C" int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particl
         f.tail = (uint32_t)(n_slots % FLAT_SLOTS);
         f.ctr0 = ctr0;
         void *args[] = {&f};
-        const hipError_t e = hipLaunchKernel(flat, dim3((uint32_t)flat_grid), dim3(256), args, 0,
+        const Grid2 g = grid_2d(flat_grid);
+        const hipError_t e = hipLaunchKernel(flat, dim3(g.x, g.y), dim3(256), args, 0,
                                              static_cast<hipStream_t>(stream));
         if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; }
         return ORNG_OK;
@@ -221,13 +230,14 @@ extern "C" int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particl
     a.draws = draws;
     a.ctr0 = ctr0;
     a.n_iters = n_iters;
-    a.xblocks = (n_particles + 255) / 256;
+    a.xblocks = blocks_for(n_particles, 256);
     // about 64K workgroups in all, at least one iteration each
     const uint64_t want_tb = std::max<uint64_t>(1, 65536 / a.xblocks);
     a.iters_per_wg = (uint32_t)std::max<uint64_t>(1, (n_iters + want_tb - 1) / want_tb);
     const uint64_t tblocks = (n_iters + a.iters_per_wg - 1) / a.iters_per_wg;
     const uint64_t grid = tblocks * a.xblocks;
-    if (grid > 0x7FFFFFFFull) return ORNG_ERANGE;
+    if (grid > 0xFFFF0000ull) return ORNG_ERANGE;
+    a.n_wgs = (uint32_t)grid;
     void *kern = nullptr;
 #define ORNG_PK(G) (draws == 3 ? reinterpret_cast<void *>(&k_particles<G, 3>) \
                                : reinterpret_cast<void *>(&k_particles<G, 0>))
@@ -245,7 +255,8 @@ extern "C" int orng_particle_streams(int gen, uint64_t seed0, uint32_t n_particl
     }
 #undef ORNG_PK
     void *args[] = {&a};
-    const hipError_t e = hipLaunchKernel(kern, dim3((uint32_t)grid), dim3(256), args, 0,
+    const Grid2 g = grid_2d(grid);
+    const hipError_t e = hipLaunchKernel(kern, dim3(g.x, g.y), dim3(256), args, 0,
                                          static_cast<hipStream_t>(stream));
     if (e != hipSuccess) { set_hip_error(e); return ORNG_EHIP; }
     return ORNG_OK;

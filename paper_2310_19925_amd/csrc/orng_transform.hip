@@ -9,7 +9,7 @@ namespace orng {
 
 __global__ __launch_bounds__(256) void k_normal_pairs(const uint32_t *x0, const uint32_t *x1,
                                                       uint64_t n, float *z0, float *z1) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = (uint64_t)flat_block() * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float a, b;
     normal_pair(x0[i], x1[i], a, b);
@@ -26,8 +26,8 @@ extern "C" int orng_normal_pairs(const uint32_t *d_x0, const uint32_t *d_x1, uin
     for (const void *p : ptrs)
         if (!p || (reinterpret_cast<uintptr_t>(p) & 3u)) return ORNG_EINVAL;
     if (n > (1ull << 40)) return ORNG_ERANGE;
-    const uint64_t grid = (n + 255) / 256;
-    orng::k_normal_pairs<<<dim3((uint32_t)grid), dim3(256), 0, static_cast<hipStream_t>(stream)>>>(
+    const orng::Grid2 g = orng::grid_2d((n + 255) / 256);
+    orng::k_normal_pairs<<<dim3(g.x, g.y), dim3(256), 0, static_cast<hipStream_t>(stream)>>>(
         d_x0, d_x1, n, d_z0, d_z1);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {

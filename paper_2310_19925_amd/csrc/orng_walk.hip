@@ -76,8 +76,10 @@ template <int DIM>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
     constexpr uint32_t GB = DIM == 3 ? 3 : 1;   // Philox blocks per group
     constexpr uint32_t GS = 4 * GB / DIM;       // steps per group
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = i < a.n;
+    const uint64_t i64 = (uint64_t)flat_block() * blockDim.x + threadIdx.x;
+    if ((uint64_t)flat_block() * blockDim.x >= a.n) return;  // a whole workgroup past the end
+    const uint32_t i = (uint32_t)i64;
+    const bool live = i64 < a.n;
     float x[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) x[d] = live ? a.pos[(uint64_t)d * a.n + i] : 0.0f;
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
 }
 
 __global__ void k_zero_f64(double *p, uint32_t n) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = (uint64_t)flat_block() * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0;
 }
 
@@ -150,18 +152,19 @@ hipError_t launch_walk(uint64_t seed, uint32_t ctr0, uint32_t n, uint32_t dim, u
         if (nsnap == 0) {
             a.msd_every = 0;
         } else {
-            k_zero_f64<<<(nsnap + 255) / 256, 256, 0, s>>>(msd, nsnap);
+            const Grid2 gz = grid_2d(blocks_for(nsnap, 256));
+            k_zero_f64<<<dim3(gz.x, gz.y), 256, 0, s>>>(msd, nsnap);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
     }
     const uint32_t wg = 256;
-    const uint32_t grid = (n + wg - 1) / wg;
+    const Grid2 grid = grid_2d(blocks_for(n, wg));
     void *args[] = {&a};
     void *k = dim == 1 ? reinterpret_cast<void *>(&k_walk<1>)
             : dim == 2 ? reinterpret_cast<void *>(&k_walk<2>)
                        : reinterpret_cast<void *>(&k_walk<3>);
-    return hipLaunchKernel(k, dim3(grid), dim3(wg), args, 0, s);
+    return hipLaunchKernel(k, dim3(grid.x, grid.y), dim3(wg), args, 0, s);
 }
 
 }  // namespace orng

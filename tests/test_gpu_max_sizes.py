@@ -1,0 +1,104 @@
+"""GPU calls whose grids pass one dispatch dimension's limit of 2^32
+work-items (64 GiB outputs in one call, which a 288 GB device holds): the
+multi-stream fill and integer-range fill cap their grid-strided grids, the
+element-wise normal transform and the flat micro-stream schedule launch
+two-dimensional grids.  Sampled streams at both ends of each output are
+compared with the oracle, and nothing is written past the end."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_19925_amd import orng
+    return orng
+
+
+GUARD = 4096
+
+
+def _free():
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def test_fill_multi_beyond_one_grid_dimension(R, O):
+    """2^26 + 1000 Philox streams of 256 words: one 1,024-word span each, so
+    the uncapped one-wave-per-span grid would be 2^32 + 64,000 work-items."""
+    S, L = 2**26 + 1000, 256
+    print("fill_multi %d streams x %d words" % (S, L), flush=True)
+    out = torch.full((S * L + GUARD,), -1, dtype=torch.int32, device="cuda")
+    R.orng_fill_multi(0, 0, 9, 0, S, 0, L, out)
+    torch.cuda.synchronize()
+    assert np.all(out[S * L:].cpu().numpy() == -1)
+    for i0 in (0, 2**25 + 7, S - 50):
+        got = out[i0 * L:(i0 + 50) * L].cpu().numpy().view(np.uint32)
+        ref = O.fill_multi(0, 0, 9, i0, 50, 0, L).view(np.uint32)
+        assert np.array_equal(got, ref), i0
+    del out
+    _free()
+
+
+def test_fill_range_beyond_one_grid_dimension(R, O):
+    """2^26 + 1000 Philox streams of 256 integers (512 words): one span of
+    256 samples each at the built-in shape's 16 groups per span, so the
+    capped grid still loops."""
+    S, L = 2**26 + 1000, 256
+    print("fill_range %d streams x %d samples" % (S, L), flush=True)
+    out = torch.full((S * L + GUARD,), -1, dtype=torch.int32, device="cuda")
+    R.orng_fill_range(0, 11, 0, S, 0, L, -5, 1000, out)
+    torch.cuda.synchronize()
+    assert np.all(out[S * L:].cpu().numpy() == -1)
+    for i0 in (0, S - 50):
+        got = out[i0 * L:(i0 + 50) * L].cpu().numpy()
+        assert np.array_equal(got, O.fill_range(0, 11, i0, 50, 0, L, -5, 1000)), i0
+    del out
+    _free()
+
+
+def test_normal_pairs_beyond_one_grid_dimension(R, O):
+    """2^32 + 1000 pairs (four arrays of 16 GiB): 2^24 + 4 workgroups."""
+    n = 2**32 + 1000
+    print("normal_pairs n=%d" % n, flush=True)
+    x0 = torch.empty(n, dtype=torch.int32, device="cuda")
+    x1 = torch.empty(n, dtype=torch.int32, device="cuda")
+    # a stream holds 2^32 words: the last 1,000 come from a second stream
+    for x, c in ((x0, 1), (x1, 2)):
+        R.orng_fill(0, 0, 21, c, 0, 2**32, x)
+        R.orng_fill(0, 0, 21, c + 2, 0, n - 2**32, x[2**32:])
+    z0 = torch.full((n + GUARD,), -7.0, dtype=torch.float32, device="cuda")
+    z1 = torch.full((n + GUARD,), -7.0, dtype=torch.float32, device="cuda")
+    R.orng_normal_pairs(x0, x1, n, z0, z1)
+    torch.cuda.synchronize()
+    assert np.all(z0[n:].cpu().numpy() == -7.0) and np.all(z1[n:].cpu().numpy() == -7.0)
+    for i0 in (0, 2**32 - 500, n - 500):
+        a = x0[i0:i0 + 500].cpu().numpy().view(np.uint32)
+        b = x1[i0:i0 + 500].cpu().numpy().view(np.uint32)
+        r0, r1 = O.normal_pair_n(a, b)
+        assert np.array_equal(z0[i0:i0 + 500].cpu().numpy().view(np.uint32), r0.view(np.uint32))
+        assert np.array_equal(z1[i0:i0 + 500].cpu().numpy().view(np.uint32), r1.view(np.uint32))
+    del x0, x1, z0, z1
+    _free()
+
+
+def test_flat_micro_streams_beyond_one_grid_dimension(R, O):
+    """2^16 particles x (2^18 + 5) iterations, one word each (64 GiB): the
+    flat schedule's 2^24 + 320 workgroups go out as a two-row grid."""
+    P, T = 2**16, 2**18 + 5
+    n = P * T
+    print("particle_streams %d x %d" % (P, T), flush=True)
+    out = torch.full((n + GUARD,), -1, dtype=torch.int32, device="cuda")
+    R.orng_particle_streams(0, 3, P, 1, 0, T, out)
+    torch.cuda.synchronize()
+    assert np.all(out[n:].cpu().numpy() == -1)
+    for t in (0, 2**18 - 1, T - 1):
+        got = out[t * P:(t + 1) * P].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, O.particle_streams(0, 3, P, 1, t, 1)), t
+    del out
+    _free()

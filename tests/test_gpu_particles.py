@@ -115,3 +115,21 @@ def test_particle_streams_misaligned_output(R, O, gen, shift, draws):
     host = buf.cpu().numpy().view(np.uint32)
     assert np.all(host[:shift] == 0xFFFFFFFF) and host[shift + n] == 0xFFFFFFFF
     assert np.array_equal(host[shift:shift + n], O.particle_streams(gen, 7, P, draws, 11, T))
+
+
+@pytest.mark.parametrize("P", [2**32 - 1, 2**32 - 1025])
+def test_particle_streams_largest_particle_counts(R, O, P):
+    """2^32 - 1 particles (the lane schedule, whose workgroup count is rounded
+    up without wrapping) and 2^32 - 1025 (the largest count the flat schedule
+    takes), one word each for one iteration (16 GiB): the first and last
+    1,000 particles against the oracle, nothing written past the end."""
+    print("micro-streams P=%d" % P, flush=True)
+    out = torch.full((P + 1024,), -1, dtype=torch.int32, device="cuda")
+    R.orng_particle_streams(0, 5, P, 1, 3, 1, out)
+    torch.cuda.synchronize()
+    assert np.all(out[P:].cpu().numpy() == -1)
+    for p0 in (0, P - 1000):
+        got = out[p0:p0 + 1000].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, O.particle_streams(0, 5 + p0, 1000, 1, 3, 1)), p0
+    del out
+    torch.cuda.empty_cache()

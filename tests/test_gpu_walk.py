@@ -113,3 +113,22 @@ def test_walk_all_particles_100_steps(R, O):
     ref, _ = O.brownian(seed, 0, n_particles=n, dim=dim, n_steps=100, dt=cfg["dt"], D=cfg["D"])
     bad = np.nonzero((got.view(np.uint32) != ref.view(np.uint32)).any(axis=0))[0]
     assert bad.size == 0, "%d particles differ, first %d" % (bad.size, bad[0])
+
+
+def test_walk_largest_particle_count(R, O):
+    """2^32 - 1 particles (1-D, 16 GiB of positions), two steps: the grid
+    covers every particle (its workgroup count is rounded up without
+    wrapping); the first and last 1,000 particles against the oracle, whose
+    particle i0 + j of a walk with counter base 0 is particle j of one with
+    counter base i0."""
+    n = 2**32 - 1
+    print("walk n=%d dim=1 steps=2" % n, flush=True)
+    pos = torch.zeros((1, n), dtype=torch.float32, device="cuda")
+    R.orng_brownian(77, 0, n, 1, 0, 2, 1e-3, 1.0, pos, None, 0)
+    torch.cuda.synchronize()
+    for i0 in (0, n - 1000):
+        got = pos[0, i0:i0 + 1000].cpu().numpy()
+        ref, _ = O.brownian(77, i0, n_particles=1000, dim=1, n_steps=2, dt=1e-3, D=1.0)
+        assert np.array_equal(got.view(np.uint32), ref.ravel().view(np.uint32)), i0
+    del pos
+    torch.cuda.empty_cache()

@@ -225,6 +225,9 @@ def test_serve_create_validation(L):
                                C.byref(h)) == EINVAL
     assert L.orng_serve_create(C.cast(C.pointer(cfg_t(FAKE + 8, 1 << 20, 0, 0, 0)), C.c_void_p),
                                C.byref(h)) == EINVAL
+    # a step of more than 2^34 words
+    assert L.orng_serve_create(C.cast(C.pointer(cfg_t(None, 1 << 20, 0, 0, 2**34 + 1)),
+                                      C.c_void_p), C.byref(h)) == EINVAL
 
 
 def test_fill_range_validation(L):
