@@ -2,8 +2,9 @@
 work-items (64 GiB outputs in one call, which a 288 GB device holds): the
 multi-stream fill and integer-range fill cap their grid-strided grids, the
 element-wise normal transform and the flat micro-stream schedule launch
-two-dimensional grids.  Sampled streams at both ends of each output are
-compared with the oracle, and nothing is written past the end."""
+two-dimensional grids.  Also a whole stream (2^32 words) in one fill and
+2^31 integers in one range fill.  Sampled streams at both ends of each output
+are compared with the oracle, and nothing is written past the end."""
 import numpy as np
 import pytest
 
@@ -100,5 +101,42 @@ def test_flat_micro_streams_beyond_one_grid_dimension(R, O):
     for t in (0, 2**18 - 1, T - 1):
         got = out[t * P:(t + 1) * P].cpu().numpy().view(np.uint32)
         assert np.array_equal(got, O.particle_streams(0, 3, P, 1, t, 1)), t
+    del out
+    _free()
+
+
+@pytest.mark.parametrize("gen,dist", [(0, 0), (3, 1), (4, 0), (7, 2), (1, 3), (8, 4)])
+def test_whole_stream_in_one_fill(R, O, gen, dist):
+    """Every word of one stream in one call (2^32 words: 2^32 float32
+    samples, or 2^31 float64 ones; 16 GiB): the first and last 20,000 samples
+    against the oracle, nothing written past the end."""
+    n = 2**32 if dist < 3 else 2**31
+    esz = 4 if dist < 3 else 8
+    print("whole stream gen=%d dist=%d n=%d" % (gen, dist, n), flush=True)
+    out = torch.full((n * esz // 4 + GUARD,), -1, dtype=torch.int32, device="cuda")
+    R.orng_fill(gen, dist, 0x5EED, 7, 0, n, out)
+    torch.cuda.synchronize()
+    assert np.all(out[n * esz // 4:].cpu().numpy() == -1)
+    for s0 in (0, n - 20000):
+        w0, w1 = s0 * esz // 4, (s0 + 20000) * esz // 4
+        got = out[w0:w1].cpu().numpy().view(np.uint32)
+        ref = O.fill(gen, dist, 0x5EED, 7, s0, 20000)
+        assert np.array_equal(got, ref.view(np.uint32)), s0
+    del out
+    _free()
+
+
+@pytest.mark.parametrize("gen", [0, 4])
+def test_whole_stream_of_integers_in_one_fill(R, O, gen):
+    """2^31 integers in [lo, hi) (every word pair of one stream, 8 GiB)."""
+    n = 2**31
+    print("whole-stream range gen=%d" % gen, flush=True)
+    out = torch.full((n + GUARD,), -1, dtype=torch.int32, device="cuda")
+    R.orng_fill_range(gen, 0x5EED, 7, 1, 0, n, -3, 2**31 - 1, out)
+    torch.cuda.synchronize()
+    assert np.all(out[n:].cpu().numpy() == -1)
+    for s0 in (0, n - 20000):
+        got = out[s0:s0 + 20000].cpu().numpy()
+        assert np.array_equal(got, O.fill_range(gen, 0x5EED, 7, 1, s0, 20000, -3, 2**31 - 1)), s0
     del out
     _free()
