@@ -19,9 +19,8 @@
 //   6.9 TB/s and 3 KiB pieces, the lane schedule's share, at 5.6 TB/s).
 //   Measured against the lane schedule on 16,000 x 3 x 22,369 words, the
 //   flat one is 17-18% faster for the Threefry4x32 forms and 2% for Philox4x32
-//   and Squares64, and 2-7% slower for the other generators, which keep the
-//   lane schedule: there the key schedule per slot, or Tyche's seeding, costs
-//   more than the store pattern gains.
+//   and Squares64, and 2-7% slower for the other generators (the same kernel
+//   built for them), which keep the lane schedule.
 // - lane per particle (any other shape): a lane forms its key schedule once
 //   (it depends only on the seed) and runs a chunk of iterations; the wave's
 //   micro-streams of an iteration are contiguous in the output and are stored
