@@ -133,3 +133,13 @@ def test_particle_streams_largest_particle_counts(R, O, P):
         assert np.array_equal(got, O.particle_streams(0, 5 + p0, 1000, 1, 3, 1)), p0
     del out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("draws", [1, 3, 4])
+def test_particle_streams_flat_seeds_across_a_high_word(R, O, draws):
+    """Philox4x32 micro-streams on the flat schedule whose seeds seed0 + p
+    pass 2^32 inside a workgroup (the carry into the key's high word differs
+    between its lanes)."""
+    P, T, s0 = 5000, 3, 2**32 - 700
+    got = _run(R, 0, s0, P, draws, 11, T)
+    assert np.array_equal(got, O.particle_streams(0, s0, P, draws, 11, T))
