@@ -11,7 +11,11 @@
 - the request-record checks of the batched and served paths (host-only
   header): 200,000 requests drawn on and around every boundary, each
   compared with the documented rules (return code, integer-range bounds,
-  output alignment class).
+  output alignment class);
+- the serving loop's scheduling rules (host-only header): request tiling
+  over random ranges and step planning over random request sets admitted
+  over time, checked against their stated properties until every tile is
+  scheduled once.
 """
 import os
 import shutil
@@ -135,3 +139,10 @@ def test_request_checks_under_sanitizers(tmp_path):
     # the draw reaches every outcome often, and every alignment class
     assert min(codes.get(c, 0) for c in (0, -1, -2)) > 5000, codes
     assert min(aligned) > 1000, aligned
+
+
+def test_serve_scheduling_rules_under_sanitizers(tmp_path):
+    exe = _build(tmp_path, "serve_plan_check", [os.path.join(HERE, "serve_plan_check.cc")])
+    out = _run([exe, "300"]).strip()
+    assert out.startswith("OK 300 rounds"), out
+    assert int(out.split()[3]) > 10000, out  # many steps were planned
