@@ -1,8 +1,8 @@
 """GPU calls whose grids pass one dispatch dimension's limit of 2^32
 work-items (64 GiB outputs in one call, which a 288 GB device holds): the
 multi-stream fill and integer-range fill cap their grid-strided grids, the
-element-wise normal transform and the flat micro-stream schedule launch
-two-dimensional grids.  Also a whole stream (2^32 words) in one fill and
+element-wise normal transform, the flat micro-stream schedule and the 2-D
+Brownian dynamics launch two-dimensional grids.  Also a whole stream (2^32 words) in one fill and
 2^31 integers in one range fill.  Sampled streams at both ends of each output
 are compared with the oracle, and nothing is written past the end."""
 import numpy as np
@@ -139,4 +139,22 @@ def test_whole_stream_of_integers_in_one_fill(R, O, gen):
         got = out[s0:s0 + 20000].cpu().numpy()
         assert np.array_equal(got, O.fill_range(gen, 0x5EED, 7, 1, s0, 20000, -3, 2**31 - 1)), s0
     del out
+    _free()
+
+
+def test_bd2_beyond_one_grid_dimension(R, O):
+    """The 2-D Brownian dynamics on 2^31 + 1000 particles (four float64
+    arrays, 64 GiB), 3 steps from rest: 2^23 + 4 workgroups as a two-row
+    grid; the first and last 1,000 particles against the oracle (particle i
+    of a run from pid0 is particle i - i0 of one from pid0 + i0)."""
+    n = 2**31 + 1000
+    print("bd2 n=%d" % n, flush=True)
+    st = torch.zeros((4, n), dtype=torch.float64, device="cuda")
+    R.orng_bd2(9, n, 1, 3, 1e-3, 1.0, st[0], st[1], st[2], st[3], 0)
+    torch.cuda.synchronize()
+    for i0 in (0, n - 1000):
+        got = st[:, i0:i0 + 1000].cpu().numpy()
+        ref = O.bd2(9 + i0, 1000, step0=1, n_steps=3, dt=1e-3, c=1.0)
+        assert np.array_equal(got.view(np.int64), ref.view(np.int64)), i0
+    del st
     _free()
