@@ -12,12 +12,10 @@
 //   at most four words, at least 1024 particles, a 16-byte aligned output):
 //   workgroup w makes the 1024 (iteration, particle) slots 1024 w .. 1024 w +
 //   1023 of the output order, four per thread, each with its own key
-//   schedule, and stores its 4096 * draws contiguous bytes in 16-byte chunks.
-//   Every workgroup's share of the output is a whole number of 4 KiB pieces
-//   at 4 KiB offsets from the output's start (on MI355X, where consecutive
-//   workgroups run on different XCDs, a pure-store probe wrote such pieces at
-//   6.9 TB/s and 3 KiB pieces, the lane schedule's share, at 5.6 TB/s).
-//   Measured against the lane schedule on 16,000 x 3 x 22,369 words, the
+//   schedule, and stores its 4096 * draws contiguous bytes in 16-byte chunks
+//   (short-lived workgroups of independent slots, where the lane schedule
+//   keeps long-lived lanes with a key schedule each).  Measured against the
+//   lane schedule on 16,000 x 3 x 22,369 words, the
 //   flat one is 17-18% faster for the Threefry4x32 forms and 2% for Philox4x32
 //   and Squares64, and 2-7% slower for the other generators (the same kernel
 //   built for them), which keep the lane schedule.
