@@ -69,10 +69,11 @@ def test_particle_streams_flat_schedule(R, O, gen, draws, P, T):
 
 @pytest.mark.parametrize("gen", [0, 1, 5, 8])
 @pytest.mark.parametrize("shift", [1, 2, 3])
-def test_particle_streams_flat_shape_misaligned(R, O, gen, shift):
+@pytest.mark.parametrize("D", [1, 3, 4])
+def test_particle_streams_flat_shape_misaligned(R, O, gen, shift, D):
     """The flat schedule's shape with an output off the 16-byte grid takes the
     lane schedule: same words, nothing written outside the output."""
-    P, D, T = 2048, 3, 4
+    P, T = 2048, 4
     n = P * D * T
     buf = torch.full((n + shift + 1,), -1, dtype=torch.int32, device="cuda")
     R.orng_particle_streams(gen, 9, P, D, 3, T, buf.data_ptr() + 4 * shift)
