@@ -109,7 +109,7 @@ def roofs(gen, dist, n, ms):
 # calibration factors a 1 GiB device copy gives for each counter.  Valid only
 # for the kernel sources and launch table they were measured on: bench.py
 # reports null traffic when the hash of those sources differs.
-TRAFFIC_SRC_SHA = "6641b4c8b15719b3"
+TRAFFIC_SRC_SHA = "9a2c8864b6a9f0bb"
 TRAFFIC_FACTORS = (1.9999227553638532, 1.0)  # FETCH, WRITE
 TRAFFIC_KIB = {
     (0, 0): (80.4375, 4194304.0), (0, 1): (45.4375, 4195201.5), (0, 2): (63.4375, 4194307.75), (0, 3): (27.5, 4194304.0),

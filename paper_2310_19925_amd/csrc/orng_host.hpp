@@ -70,10 +70,10 @@ struct Grid2 {
 };
 constexpr Grid2 grid_2d(uint64_t blocks) {
     const uint64_t row = 65536;
-    return blocks <= row ? Grid2{(uint32_t)blocks, 1u}
-                         : Grid2{(uint32_t)((blocks + (blocks + row - 1) / row - 1) /
-                                            ((blocks + row - 1) / row)),
-                                 (uint32_t)((blocks + row - 1) / row)};
+    const uint64_t rows = (blocks + row - 1) / row;       // at least 1 for blocks > 0
+    if (rows <= 1) return Grid2{(uint32_t)blocks, 1u};
+    const uint64_t per_row = (blocks + rows - 1) / rows;  // <= row
+    return Grid2{(uint32_t)per_row, (uint32_t)rows};
 }
 static_assert(grid_2d(100).x == 100 && grid_2d(100).y == 1, "one row");
 static_assert((uint64_t)grid_2d((1ull << 32) - 1).x * grid_2d((1ull << 32) - 1).y >=
