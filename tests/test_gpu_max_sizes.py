@@ -158,3 +158,27 @@ def test_bd2_beyond_one_grid_dimension(R, O):
         assert np.array_equal(got.view(np.int64), ref.view(np.int64)), i0
     del st
     _free()
+
+
+@pytest.mark.parametrize("noalloc", [False, True])
+def test_batched_whole_streams(R, O, noalloc):
+    """One batch of two whole streams: 2^32 Philox words and 2^31 Squares64
+    float64 uniforms (16 GiB each), through the batched call and its
+    allocation-free form; both ends of each output against the oracle."""
+    n0, n1 = 2**32, 2**31
+    print("batched whole streams noalloc=%s" % noalloc, flush=True)
+    a = torch.full((n0 + GUARD,), -1, dtype=torch.int32, device="cuda")
+    b = torch.full((2 * n1 + GUARD,), -1, dtype=torch.int32, device="cuda")
+    reqs = R.make_requests([0, 8], [0, 3], [0x5EED, 77], [3, 4], 0, [n0, n1],
+                           [a.data_ptr(), b.data_ptr()])
+    (R.orng_fill_batched_noalloc if noalloc else R.orng_fill_batched)(reqs)
+    torch.cuda.synchronize()
+    assert np.all(a[n0:].cpu().numpy() == -1) and np.all(b[2 * n1:].cpu().numpy() == -1)
+    for s0 in (0, n0 - 20000):
+        got = a[s0:s0 + 20000].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, O.fill(0, 0, 0x5EED, 3, s0, 20000)), s0
+    for s0 in (0, n1 - 20000):
+        got = b[2 * s0:2 * (s0 + 20000)].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, O.fill(8, 3, 77, 4, s0, 20000).view(np.uint32)), s0
+    del a, b
+    _free()
