@@ -2,8 +2,9 @@
 work-items (64 GiB outputs in one call, which a 288 GB device holds): the
 multi-stream fill and integer-range fill cap their grid-strided grids, the
 element-wise normal transform, the flat micro-stream schedule and the 2-D
-Brownian dynamics launch two-dimensional grids.  Also a whole stream (2^32 words) in one fill and
-2^31 integers in one range fill.  Sampled streams at both ends of each output
+Brownian dynamics launch two-dimensional grids.  Also a whole stream (2^32 words) in one fill, 2^31
+integers in one range fill, and whole streams through the batched,
+allocation-free batched and served paths.  Sampled streams at both ends of each output
 are compared with the oracle, and nothing is written past the end."""
 import numpy as np
 import pytest
@@ -181,4 +182,36 @@ def test_batched_whole_streams(R, O, noalloc):
         got = b[2 * s0:2 * (s0 + 20000)].cpu().numpy().view(np.uint32)
         assert np.array_equal(got, O.fill(8, 3, 77, 4, s0, 20000).view(np.uint32)), s0
     del a, b
+    _free()
+
+
+def test_served_whole_stream(R, O):
+    """A served request for a whole stream (2^32 Tyche words, 16 GiB) in a
+    17 GiB arena, beside a caller-owned whole stream of 2^31 Threefry4x32
+    float64 normals: both ends of each result against the oracle."""
+    n0, n1 = 2**32, 2**31
+    print("served whole streams", flush=True)
+    arena = torch.empty((17 << 30) // 4, dtype=torch.int32, device="cuda")
+    mine = torch.full((2 * n1 + GUARD,), -1, dtype=torch.int32, device="cuda")
+    srv = R.orng_serve_create(arena.numel() * 4, arena=arena)
+    try:
+        t0 = R.orng_serve_submit(srv, 4, 0, 0x5EED, 6, 0, n0)
+        t1 = R.orng_serve_submit(srv, 1, 4, 99, 2, 0, n1, out=mine.data_ptr())
+        r0 = R.orng_serve_wait(srv, t0)
+        r1 = R.orng_serve_wait(srv, t1)
+        assert r0["status"] == 0 and r1["status"] == 0 and r0["n"] == n0 and r1["n"] == n1
+        torch.cuda.synchronize()
+        off = (r0["d_out"] - arena.data_ptr()) // 4
+        for s0 in (0, n0 - 20000):
+            got = arena[off + s0:off + s0 + 20000].cpu().numpy().view(np.uint32)
+            assert np.array_equal(got, O.fill(4, 0, 0x5EED, 6, s0, 20000)), s0
+        assert np.all(mine[2 * n1:].cpu().numpy() == -1)
+        for s0 in (0, n1 - 20000):
+            got = mine[2 * s0:2 * (s0 + 20000)].cpu().numpy().view(np.uint32)
+            assert np.array_equal(got, O.fill(1, 4, 99, 2, s0, 20000).view(np.uint32)), s0
+        R.orng_serve_release(srv, t0)
+        R.orng_serve_release(srv, t1)
+    finally:
+        R.orng_serve_destroy(srv)
+    del arena, mine
     _free()
