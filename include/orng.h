@@ -380,7 +380,10 @@ typedef struct {
 int orng_serve_create(const orng_serve_cfg_t *cfg, orng_server_t **srv);
 /* Queue a request; never blocks on the device.  req->out == NULL asks the
    server for an arena output (released by orng_serve_release); otherwise the
-   caller's buffer is written.  Errors: EINVAL/ERANGE (as orng_fill), ENOMEM
+   caller's buffer is written.  The server writes from streams of its own,
+   which do not wait for work queued on the caller's streams: a caller buffer
+   must have no pending reads or writes on any stream when it is submitted
+   (synchronize first).  Errors: EINVAL/ERANGE (as orng_fill), ENOMEM
    (output larger than the arena), EBUSY (server shutting down). */
 int orng_serve_submit(orng_server_t *srv, const orng_req_t *req, uint64_t *ticket);
 /* Non-blocking submit: the request is queued only if the server can admit it

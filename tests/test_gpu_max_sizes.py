@@ -193,6 +193,7 @@ def test_served_whole_stream(R, O):
     print("served whole streams", flush=True)
     arena = torch.empty((17 << 30) // 4, dtype=torch.int32, device="cuda")
     mine = torch.full((2 * n1 + GUARD,), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()  # the server's streams do not wait for torch's
     srv = R.orng_serve_create(arena.numel() * 4, arena=arena)
     try:
         t0 = R.orng_serve_submit(srv, 4, 0, 0x5EED, 6, 0, n0)

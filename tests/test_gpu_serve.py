@@ -73,6 +73,7 @@ def test_serve_caller_outputs_and_small_steps(R, O):
         bufs, tickets = [], []
         for q in reqs:
             b = torch.full((q["n"] + 2,), -1, dtype=torch.int32, device="cuda")
+            torch.cuda.synchronize()  # the server's streams do not wait for torch's
             bufs.append(b)
             tickets.append(R.orng_serve_submit(srv, out=b.data_ptr() + 4, **q))
         for q, t, b in zip(reqs, tickets, bufs):
@@ -169,6 +170,7 @@ def test_serve_errors(R):
 
 def test_serve_destroy_drains_in_flight(R, O):
     out = torch.full((1 << 20,), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()  # the server's streams do not wait for torch's
     srv = R.orng_serve_create(1 << 24)
     for k in range(8):
         R.orng_serve_submit(srv, 4, 1, k, k, 0, 1 << 17, out=out.data_ptr() + k * (1 << 19))
@@ -330,6 +332,7 @@ def test_serve_later_step_failure_keeps_finished_results(R, O, monkeypatch):
     EHIP, and nothing is left running."""
     print("serve: injected failure of step 3", flush=True)
     outs = torch.full((40, 1 << 14), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()  # the server's streams do not wait for torch's
     srv = _failing_server(R, monkeypatch, 3, arena_bytes=1 << 20, step_words=1 << 15)
     qs = [dict(gen=k % 9, dist=k % 3, seed=1000 + k, ctr=k, offset=3 * k, n=(1 << 14) - k)
           for k in range(40)]
@@ -455,6 +458,7 @@ def test_serve_integer_ranges(R, O):
             if k % 3 == 0:  # caller buffer, one word off the 16-byte grid (two for float64)
                 sh = 2 if q["dist"] in (3, 4) else 1
                 b = torch.full((w + sh + 1,), -1, dtype=torch.int32, device="cuda")
+                torch.cuda.synchronize()  # the server's streams do not wait for torch's
                 bufs.append((b, sh, w))
                 tickets.append(R.orng_serve_submit(srv, out=b.data_ptr() + 4 * sh, **q))
             else:
