@@ -120,7 +120,10 @@ const uint64_t TYCHE_TILE = 16384, TYCHE_LANES = 64, TYCHE_BLOCKS = 64;
  * seed, without saying how it becomes a key).  Here the 64-bit seed is mapped
  * through one SplitMix64 output step (Steele, Lea, Flood, OOPSLA 2014: add the
  * 64-bit golden-ratio increment, then the two xor-shift-multiply rounds and a
- * final xor-shift) and the low bit is forced to 1.  Parity unpinned.
+ * final xor-shift) and the low bit is forced to 1.  The finalizer (its
+ * constants and shifts) is pinned to pybind11's own implementation of it
+ * (test_squares_key_vs_pybind11_splitmix64); the increment and the low bit
+ * are the reading.
  * ------------------------------------------------------------------------- */
 
 /* ---------------------------------------------------------------------------
