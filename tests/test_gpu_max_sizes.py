@@ -2,10 +2,11 @@
 work-items (64 GiB outputs in one call, which a 288 GB device holds): the
 multi-stream fill and integer-range fill cap their grid-strided grids, the
 element-wise normal transform, the flat micro-stream schedule and the 2-D
-Brownian dynamics launch two-dimensional grids.  Also a whole stream (2^32 words) in one fill, 2^31
-integers in one range fill, and whole streams through the batched,
-allocation-free batched and served paths.  Sampled streams at both ends of each output
-are compared with the oracle, and nothing is written past the end."""
+Brownian dynamics launch two-dimensional grids.  Also a whole stream (2^32
+words) in one fill, 2^31 integers in one range fill, and whole streams
+through the batched, allocation-free batched and served paths.  Sampled
+streams at both ends of each output are compared with the oracle, and nothing
+is written past the end."""
 import numpy as np
 import pytest
 
